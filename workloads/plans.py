@@ -1,0 +1,181 @@
+"""Contraction plans for the time-first 2D grid network (input data only).
+
+A plan says *in which order* the per-qubit world-line tensors are contracted,
+which grid bonds are cut (sliced), and which output qubits stay open.  It holds
+no arithmetic of the method; both the product path and the oracle receive the
+same plan and must give the same amplitudes for any valid plan (the amplitude
+is plan-invariant in exact arithmetic).
+
+Plan dictionary:
+    steps : list of [lhs, rhs] node ids in execution order.  Ids 0..n-1 are the
+            qubits' world-line tensors (row-major qubit ids); id n+i is the
+            result of step i.  Every node except the last result is consumed
+            exactly once.
+    cuts  : list of [q0, q1, bit_lo, nbits]: on grid edge (q0 < q1), the bond
+            bits bit_lo .. bit_lo+nbits-1 (bond bit j belongs to the j-th two-qubit
+            gate on that edge in time order) are fixed per slice.  The slice id
+            concatenates the cut values, first listed cut most significant, and
+            within a cut bond bit bit_lo is the most significant.
+    open  : qubit ids whose output leg stays open; the root tensor enumerates
+            all 2^k completions, the first listed open qubit most significant.
+
+Orders follow the paper's recipe (Sec. III-A, Fig. 3 caption; Sec. III-D):
+build a few large regions, contract them with each other in a handful of
+large, high-arithmetic-intensity contractions, then absorb the remaining cells
+one at a time; keep cut bonds on the region boundary.
+"""
+from __future__ import annotations
+
+from collections import Counter
+from typing import Dict, Iterable, List, Sequence, Tuple
+
+from .circuits import Circuit
+
+
+class PlanBuilder:
+    """Tracks open bond bits of each node so orders can be chosen by size."""
+
+    def __init__(self, circ: Circuit, cuts: Sequence[Sequence[int]] = (), open_qubits: Sequence[int] = ()):
+        self.circ = circ
+        self.n = circ.n_qubits
+        self.qid = circ.qubit_of()
+        self.site = {v: k for k, v in self.qid.items()}
+        cnt = Counter(op.qubits for op in circ.ops if len(op.qubits) == 2)
+        cut_bits = Counter()
+        for q0, q1, lo, nb in cuts:
+            cut_bits[(min(q0, q1), max(q0, q1))] += nb
+        self.edge_bits = {e: c - cut_bits.get(e, 0) for e, c in cnt.items()}
+        self.cuts = [list(c) for c in cuts]
+        self.open = list(open_qubits)
+        self.members: Dict[int, frozenset] = {q: frozenset([q]) for q in range(self.n)}
+        self.steps: List[List[int]] = []
+        self.alive = set(range(self.n))
+
+    def bits_of(self, members: Iterable[int]) -> int:
+        s = set(members)
+        b = sum(1 for q in s if q in self.open)
+        for (q0, q1), nb in self.edge_bits.items():
+            if (q0 in s) != (q1 in s):
+                b += nb
+        return b
+
+    def contract(self, a: int, b: int) -> int:
+        assert a in self.alive and b in self.alive and a != b
+        nid = self.n + len(self.steps)
+        self.steps.append([a, b])
+        self.members[nid] = self.members[a] | self.members[b]
+        self.alive -= {a, b}
+        self.alive.add(nid)
+        return nid
+
+    def node_of_site(self, r: int, c: int) -> int:
+        return self.qid[(r, c)]
+
+    def chain(self, sites: Sequence[Tuple[int, int]]) -> int:
+        """Absorb the listed sites one after another into a running tensor."""
+        cur = self.node_of_site(*sites[0])
+        for rc in sites[1:]:
+            cur = self.contract(cur, self.node_of_site(*rc))
+        return cur
+
+    def greedy_region(self, region: Sequence[Tuple[int, int]], start: Tuple[int, int],
+                      last: Sequence[Tuple[int, int]] = (), into: int = None) -> int:
+        """Grow from `start` (or from node `into`), each time absorbing the adjacent
+        cell of `region` that gives the smallest result; cells in `last` go last."""
+        remaining = [rc for rc in region if rc != start or into is not None]
+        if into is None:
+            cur = self.node_of_site(*start)
+            cur_sites = {start}
+        else:
+            cur = into
+            cur_sites = {self.site[q] for q in self.members[into]}
+        last = set(last)
+        while remaining:
+            def adjacent(rc):
+                r, c = rc
+                return any((r + dr, c + dc) in cur_sites for dr, dc in ((1, 0), (-1, 0), (0, 1), (0, -1)))
+            cands = [rc for rc in remaining if adjacent(rc)] or list(remaining)
+            pref = [rc for rc in cands if rc not in last] or cands
+            def score(rc):
+                mem = self.members[cur] | {self.node_of_site(*rc)}
+                return (self.bits_of(mem), rc)
+            best = min(pref, key=score)
+            cur = self.contract(cur, self.node_of_site(*best))
+            cur_sites.add(best)
+            remaining.remove(best)
+        return cur
+
+    def plan(self) -> dict:
+        assert len(self.alive) == 1, f"plan leaves {len(self.alive)} nodes"
+        return {"steps": [list(s) for s in self.steps], "cuts": [list(c) for c in self.cuts],
+                "open": list(self.open)}
+
+    def sizes(self) -> List[int]:
+        """Bits of every step result, in step order."""
+        return [self.bits_of(self.members[self.n + i]) for i in range(len(self.steps))]
+
+
+def snake_order(rows: int, cols: int, removed: Sequence[Tuple[int, int]] = ()) -> List[Tuple[int, int]]:
+    rem = set(removed)
+    out = []
+    for r in range(rows):
+        cs = range(cols) if r % 2 == 0 else range(cols - 1, -1, -1)
+        out.extend((r, c) for c in cs if (r, c) not in rem)
+    return out
+
+
+def sweep_plan(circ: Circuit, open_qubits: Sequence[int] = (), cuts: Sequence[Sequence[int]] = (),
+               by: str = "row") -> dict:
+    """Row-major (or column-major) sweep: absorb every cell into one running tensor."""
+    pb = PlanBuilder(circ, cuts, open_qubits)
+    if by == "row":
+        sites = [(r, c) for r in range(circ.rows) for c in range(circ.cols)]
+    else:
+        sites = [(r, c) for c in range(circ.cols) for r in range(circ.rows)]
+    rem = set(circ.removed)
+    pb.chain([s for s in sites if s not in rem])
+    return pb.plan()
+
+
+def region_plan(circ: Circuit, split_row: int, split_col: int, cuts: Sequence[Sequence[int]] = (),
+                open_sites: Sequence[Tuple[int, int]] = ()) -> Tuple[dict, PlanBuilder]:
+    """Regions A (top-left), B (top-right), D (bottom-left), C (bottom-right).
+
+    A, B and D are grown greedily from their outer corners; then A x B, then
+    (AB) x D; the C cells are absorbed one at a time, open cells last.
+    """
+    R, Cc = circ.rows, circ.cols
+    qid = circ.qubit_of()
+    open_q = [qid[s] for s in open_sites]
+    pb = PlanBuilder(circ, cuts, open_q)
+    A = [(r, c) for r in range(split_row) for c in range(split_col)]
+    B = [(r, c) for r in range(split_row) for c in range(split_col, Cc)]
+    D = [(r, c) for r in range(split_row, R) for c in range(split_col)]
+    C = [(r, c) for r in range(split_row, R) for c in range(split_col, Cc)]
+    a = pb.greedy_region(A, (0, 0))
+    b = pb.greedy_region(B, (0, Cc - 1))
+    ab = pb.contract(a, b)
+    d = pb.greedy_region(D, (R - 1, 0))
+    abd = pb.contract(ab, d)
+    pb.greedy_region(C, None, last=open_sites, into=abd)
+    return pb.plan(), pb
+
+
+# --- the benchmark workloads -------------------------------------------------
+
+C4_OPEN_SITES = ((5, 4), (5, 5), (5, 6), (6, 4), (6, 5), (6, 6))
+
+
+def plan_7x7(circ: Circuit, depth: int) -> Tuple[dict, PlanBuilder]:
+    """7x7 grid: regions split after row 3 and column 3 (paper Fig. 3 layout).
+
+    depth 32 (bond 16): one whole cut on (6,2)-(6,3) -> 16 slices.
+    depth 40 (bond 32): whole cuts on (2,6)-(3,6) and (6,2)-(6,3) -> 1024 slices.
+    Six output qubits in the bottom-right corner stay open (64 amplitudes/pass).
+    """
+    qid = circ.qubit_of()
+    nb = depth // 8
+    cut_b = [min(qid[(2, 6)], qid[(3, 6)]), max(qid[(2, 6)], qid[(3, 6)]), 0, nb]
+    cut_d = [min(qid[(6, 2)], qid[(6, 3)]), max(qid[(6, 2)], qid[(6, 3)]), 0, nb]
+    cuts = [cut_d] if depth <= 32 else [cut_b, cut_d]
+    return region_plan(circ, 3, 3, cuts, C4_OPEN_SITES)
