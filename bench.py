@@ -1,0 +1,187 @@
+"""Benchmark: amplitudes/s and complex Tflop/s of the 7x7 (1+40+1) random circuit (bond 32),
+split-BF16 (3 products) beside plain FP32, on one MI355X.
+
+One step = one bitstring prefix with 6 open output qubits (64 amplitudes, paper Sec. III-B)
+contracted over 6 of the 1024 slices (the paper's fidelity 6/1024 per amplitude, Sec. V).
+Prints one JSON line.  Inputs are seeded synthetic circuits from the workloads package
+(the paper's circuit files are not used).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_BF16 = 2516.6  # TFLOP/s, dense BF16 MFMA, MI355X
+PEAK_FP32 = 157.3   # TFLOP/s, FP32 MFMA / vector, MI355X
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--slices", type=int, default=6, help="slices per step (fidelity slices/1024)")
+    ap.add_argument("--fp32-steps", type=int, default=1)
+    ap.add_argument("--cpu-sample-steps", type=int, default=5,
+                    help="plan steps of the oracle timed for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-subcheck", action="store_true")
+    return ap.parse_args()
+
+
+def sub_check(ctx):
+    """Relative amplitude error against the FP64 state vector on a 4x4 (1+40+1) circuit
+    (bond 32, as in the 7x7 workload), per precision."""
+    import torch
+    from oracle import sv
+    from oracle.metrics import rel_err
+    from paper_1905_00444_amd import Circuit, Plan
+    from workloads.bitstrings import random_bitstrings
+    from workloads.circuits import generate
+    from workloads.plans import region_plan
+    c = generate(4, 4, 40, 0)
+    plan, _ = region_plan(c, 2, 2, [], [(3, 2), (3, 3)])
+    bits = random_bitstrings(64, 16, 1)
+    ref = sv.open_amplitudes(c.to_text(), bits, plan["open"])
+    out = {}
+    for prec in ("fp32", "bf16x3", "fp16"):
+        p = Plan(ctx, Circuit(ctx, c.to_text()), plan, prec)
+        got = p.amplitudes(bits)
+        torch.cuda.synchronize()
+        out[prec] = rel_err(got.cpu().numpy(), ref)
+    return out
+
+
+def cpu_baseline(circ, plan, pb, bits_row, flops_per_step, n_amp, n_steps):
+    """Time the FP64 oracle on the first `n_steps` contractions of slice 0 (a bounded sample
+    of the same workload) and scale its flop rate to amplitudes/s of one bench step."""
+    from oracle import tn
+    text = circ.to_text()
+    t0 = time.perf_counter()
+    tn.partial_contract(text, bits_row, plan, 0, n_steps)
+    dt = time.perf_counter() - t0
+    fl = 0.0
+    for (a, b), vc in list(zip(plan["steps"], pb.sizes()))[:n_steps]:
+        va, vb = pb.bits_of(pb.members[a]), pb.bits_of(pb.members[b])
+        fl += 8 * 2.0 ** ((va + vb + vc) / 2)
+    rate = fl / dt
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": n_amp * rate / flops_per_step, "unit": "amplitudes/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 numpy oracle: first {n_steps} contractions of slice 0 of the 7x7 (1+40+1) plan "
+                      f"({fl:.3e} flop in {dt:.1f} s = {rate / 1e9:.1f} GFLOP/s), scaled by flops to one step "
+                      f"({flops_per_step:.3e} flop, {n_amp} amplitudes)",
+            "fp64_gflops": rate / 1e9}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "single-GPU build: only --gpus 1 is supported; slices shard across GPUs "
+                                   "with no communication but that path is not built"}))
+        return 2
+    import torch
+    from paper_1905_00444_amd import Context, Circuit, Plan, profile_enable, profile_read
+    from workloads.bitstrings import random_bitstrings
+    from workloads.circuits import generate
+    from workloads.plans import plan_7x7
+
+    print("bench: building 7x7 (1+40+1) workload", file=sys.stderr, flush=True)
+    circ = generate(7, 7, 40, 0)
+    plan, pb = plan_7x7(circ, 40)
+    bits = random_bitstrings(64, 49, 1)
+    ctx = Context(0)
+    cobj = Circuit(ctx, circ.to_text())
+    plans = {p: Plan(ctx, cobj, plan, p) for p in ("bf16x3", "fp32")}
+    info = plans["bf16x3"].info()
+    S = args.slices
+    flops_step = plans["bf16x3"].flops(0, S)
+    n_amp = 2 ** info["n_open"]
+    ctx.ensure_workspace(info["workspace_bytes"])
+
+    def run(prec, i):
+        return plans[prec].amplitudes(bits[i % len(bits):i % len(bits) + 1], 0, S)
+
+    results = {}
+    for prec, steps in (("bf16x3", args.steps), ("fp32", args.fp32_steps)):
+        for w in range(args.warmup):
+            run(prec, w)
+            torch.cuda.synchronize()
+            print(f"bench: warmup {prec} {w} done", file=sys.stderr, flush=True)
+        profile_enable(ctx, True)
+        profile_read(ctx, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        amps = []
+        for i in range(steps):
+            amps.append(run(prec, i))
+            if prec == "bf16x3":
+                torch.cuda.synchronize()
+                print(f"bench: step {i} done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        gms, glaunch, gflops = profile_read(ctx, reset=True)
+        profile_enable(ctx, False)
+        results[prec] = {"s": dt, "steps": steps, "amps": torch.cat(amps).cpu().numpy(),
+                         "gemm_ms": gms, "gemm_launches": glaunch, "gemm_flops": gflops}
+        print(f"bench: {prec} {steps} steps in {dt:.2f} s", file=sys.stderr, flush=True)
+
+    bf, fp = results["bf16x3"], results["fp32"]
+    ms_step = bf["s"] / bf["steps"] * 1e3
+    value = n_amp * bf["steps"] / bf["s"]
+    fp_value = n_amp * fp["steps"] / fp["s"]
+    tflops = flops_step * bf["steps"] / bf["s"] / 1e12
+    fp_tflops = flops_step * fp["steps"] / fp["s"] / 1e12
+    # self-consistency of the two precisions on the same prefixes
+    k = min(len(fp["amps"]), len(bf["amps"]))
+    from numpy.linalg import norm
+    bf_vs_fp = float(norm(bf["amps"][:k] - fp["amps"][:k]) / norm(fp["amps"][:k]))
+    gemm_avg_ms = bf["gemm_ms"] / max(1, bf["gemm_launches"])
+    per_launch = bf["gemm_flops"] / max(1, bf["gemm_launches"])
+    achieved = per_launch / (gemm_avg_ms * 1e-3) / 1e12 if gemm_avg_ms > 0 else 0.0
+    peak = PEAK_BF16 / 3.0
+    rec = {
+        "metric": "amplitudes/s and complex Tflop/s, 7x7 (1+40+1) RQC; split-BF16 vs FP32 at stated rel err",
+        "value": value, "unit": "amplitudes/s (fidelity 6/1024 per amplitude)" if S == 6 else f"amplitudes/s (fidelity {S}/1024)",
+        "n_gpus": 1, "steps": bf["steps"], "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3 (FP32 accumulate)",
+        "data": "synthetic: seeded 7x7 (1+40+1) random circuit, seeded bitstring prefixes",
+        "config": {"workload": "7x7 (1+40+1) RQC, bond 32, 2 cuts (1024 slices), 6 open qubits (64 amplitudes "
+                               f"per prefix), {S} slices per step", "global_batch": n_amp, "slices_per_step": S,
+                   "parallelism": "single GPU"},
+        "complex_tflops": tflops,
+        "fp32": {"value": fp_value, "complex_tflops": fp_tflops, "steps": fp["steps"],
+                 "ms_per_step": fp["s"] / fp["steps"] * 1e3},
+        "speedup_bf16x3_vs_fp32": value / fp_value,
+        "rel_err_bf16x3_vs_fp32_same_prefixes": bf_vs_fp,
+        "flops_per_step": flops_step,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None,
+                     "kernel": "cgemm_mfma<BF16X3> on the 2^15 x 2^15 x 2^15 complex contractions",
+                     "peak_note": "2516.6 TFLOP/s dense BF16 MFMA / 3 products per complex FP32 product; "
+                                  "achieved counts algorithmic complex flops 8*M*N*K",
+                     "launches": bf["gemm_launches"], "avg_ms": gemm_avg_ms},
+    }
+    if not args.no_subcheck:
+        print("bench: 4x4 (1+40+1) sub-check vs FP64 state vector", file=sys.stderr, flush=True)
+        rec["rel_err_vs_fp64_4x4_d40"] = sub_check(ctx)
+    if not args.no_cpu:
+        print("bench: CPU oracle sample", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(circ, plan, pb, bits[0], flops_step, n_amp, args.cpu_sample_steps)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,182 @@
+/*
+ * qfmi.h -- C-ABI of the qFlex-style amplitude contraction library for AMD MI355X (gfx950).
+ *
+ * What it computes (Villalonga et al., "Establishing the Quantum Supremacy Frontier with a
+ * 281 Pflop/s Simulation", SC'19):
+ *   amplitudes a(x) = <x| U |0...0> of a random quantum circuit U on a 2D grid of qubits,
+ *   computed as a tensor network (Sec. II, tensor-network class): the circuit is first
+ *   contracted along time into one world-line tensor per qubit (Sec. III, time-first
+ *   contraction), the resulting 2D grid is sliced over cut bonds (Sec. III-A), each slice
+ *   is contracted pairwise in a given order (Sec. III-A, III-D) with transpose-GEMM
+ *   contractions (Sec. III-E, TTGT), open output qubits give a batch of amplitudes per
+ *   pass (Sec. III-B, fast sampling), and slice contributions are summed.
+ *
+ * Conventions
+ *   - Qubits are the present grid sites in row-major order.  Bitstring byte q is qubit q.
+ *   - Complex numbers are (re, im) pairs: complex64 = 2 x float, complex128 = 2 x double.
+ *   - A diagonal two-qubit gate on (q0 < q1) has diagonal entries g[2*b_q0 + b_q1].
+ *   - Grid bond (q0, q1) carries one bond bit per two-qubit gate on it; bit j is the j-th
+ *     gate in time order.
+ *   - All device pointers are HIP device addresses on the context's device.  The library
+ *     never allocates device memory: scratch comes from the caller's workspace.
+ *   - Every call is enqueued on the context's stream and returns before the GPU finishes,
+ *     unless stated otherwise.  The caller synchronises the stream before reading outputs.
+ *   - No C++ exception crosses this interface.  Functions return a qf_status; on error,
+ *     qf_last_error(ctx) returns a message.  A context is not thread-safe.
+ */
+#ifndef QFMI_H
+#define QFMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QF_OK = 0,
+  QF_ERR_ARG = -1,         /* invalid argument (null pointer, bad size, non-adjacent qubits, ...) */
+  QF_ERR_PLAN = -2,        /* invalid contraction plan or cut */
+  QF_ERR_WORKSPACE = -3,   /* workspace too small: see qf_plan_info().workspace_bytes */
+  QF_ERR_HIP = -4,         /* a HIP runtime call failed; message holds hipGetErrorString */
+  QF_ERR_UNSUPPORTED = -5, /* valid request this build does not support */
+  QF_ERR_INJECTED = -6     /* fault injected through QFMI_FAULT_AFTER_SLICES (testing) */
+} qf_status;
+
+typedef enum {
+  QF_FP32 = 0,   /* complex64 operands, FP32 MFMA products, FP32 accumulate */
+  QF_BF16X3 = 1, /* each FP32 operand split as hi + lo bfloat16; hi*hi + hi*lo + lo*hi on
+                    BF16 MFMA with FP32 accumulate */
+  QF_FP16 = 2    /* operands scaled by a power of two and rounded to FP16; FP16 MFMA with
+                    FP32 accumulate; the scale is undone exactly in FP32 */
+} qf_precision;
+
+typedef enum { QF_OP_1Q = 1, QF_OP_2Q_DIAG = 2 } qf_op_kind;
+
+/* One gate.  values: QF_OP_1Q -> row-major 2x2 complex matrix (G00, G01, G10, G11);
+ * QF_OP_2Q_DIAG -> 4 complex diagonal entries, index 2*b_q0 + b_q1, q0 < q1 adjacent. */
+typedef struct {
+  int32_t cycle;
+  int32_t kind;
+  int32_t q0;
+  int32_t q1; /* -1 for one-qubit gates */
+  float values[8];
+} qf_op;
+
+/* A cut (Sec. III-A): on grid bond (q0, q1), bond bits bit_lo .. bit_lo+nbits-1 are fixed per
+ * slice.  Slice ids concatenate the cuts' values, first cut most significant; inside a cut,
+ * bond bit bit_lo is the most significant. */
+typedef struct {
+  int32_t q0, q1, bit_lo, nbits;
+} qf_cut;
+
+enum {
+  QF_PLAN_NO_HOIST = 1 /* recompute every step for every slice (no reuse of slice-independent
+                          subtrees across slices) */
+};
+
+/* Contraction plan.  steps: 2*n_steps node ids (lhs, rhs) in execution order.  Ids 0..n-1
+ * are the qubits' world-line tensors; id n+i is the result of step i.  Every node but the
+ * last result is used exactly once.  open: qubits whose output bit stays open (Sec. III-B);
+ * the root then holds 2^n_open amplitudes, first open qubit most significant. */
+typedef struct {
+  int32_t n_steps;
+  const int32_t* steps;
+  int32_t n_cuts;
+  const qf_cut* cuts;
+  int32_t n_open;
+  const int32_t* open;
+  int32_t precision; /* qf_precision */
+  int32_t flags;     /* QF_PLAN_* */
+} qf_plan_desc;
+
+typedef struct {
+  int64_t n_slices;         /* 2^(total cut bits) */
+  int32_t n_open;           /* amplitudes per bitstring = 2^n_open */
+  int32_t n_steps;
+  int32_t peak_bits;        /* log2 of the largest tensor volume (complex elements) */
+  int32_t n_qubits;
+  double flops_per_slice;   /* sum over steps of 8*sqrt(v0*v1*v2) (paper Sec. IV) */
+  double flops_hoisted;     /* part of flops_per_slice that depends on no cut value */
+  double flops_first_slice; /* flops of the first slice of a bitstring, with reuse */
+  double flops_next_slice;  /* average flops of each later slice of the same bitstring */
+  double permute_bytes;     /* bytes read + written by permutes per slice (no reuse) */
+  size_t workspace_bytes;   /* workspace the plan needs */
+} qf_plan_info;
+
+typedef struct qf_ctx qf_ctx;
+typedef struct qf_circuit qf_circuit;
+typedef struct qf_plan qf_plan;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t, may be
+ * NULL for the null stream).  workspace/ws_bytes: caller-owned device memory (256-byte
+ * aligned) the library uses for every tensor; it may be NULL/0 now and set later. */
+qf_status qf_ctx_create(int device, void* hip_stream, void* workspace, size_t ws_bytes, qf_ctx** out);
+qf_status qf_ctx_set_workspace(qf_ctx* ctx, void* workspace, size_t ws_bytes);
+qf_status qf_ctx_set_stream(qf_ctx* ctx, void* hip_stream);
+void qf_ctx_destroy(qf_ctx* ctx);
+const char* qf_last_error(const qf_ctx* ctx);
+
+/* Circuit on a rows x cols grid; present[r*cols+c] != 0 marks a live site (NULL = all).
+ * Host arrays are copied.  Errors: QF_ERR_ARG for out-of-range or non-adjacent qubits. */
+qf_status qf_circuit_create(qf_ctx* ctx, int rows, int cols, const uint8_t* present, int n_ops,
+                            const qf_op* ops, qf_circuit** out);
+/* Replace all gate values (n_ops * 8 floats, same layout as qf_op.values). */
+qf_status qf_circuit_set_values(qf_circuit* circ, const float* values);
+void qf_circuit_destroy(qf_circuit* circ);
+
+/* Validate a plan against a circuit and lay out its workspace (host only). */
+qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* desc, qf_plan** out);
+qf_status qf_plan_info_get(const qf_plan* plan, qf_plan_info* out);
+/* Algorithmic flops (sum of 8 sqrt(v0 v1 v2) over executed steps) that qf_amplitudes performs
+ * for ONE bitstring over slices [s_begin, s_end), counting the reuse of steps whose inputs do
+ * not change from one slice to the next (host only). */
+qf_status qf_plan_flops(const qf_plan* plan, int64_t s_begin, int64_t s_end, double* flops);
+void qf_plan_destroy(qf_plan* plan);
+
+/* Amplitudes for n_batch bitstrings over slices [s_begin, s_end) (paper Sec. III-A: the
+ * amplitude is the sum over all slices; a sub-range gives a partial path sum).
+ *   bits_dev: device, n_batch x n_qubits bytes (0/1); bytes of open qubits are ignored.
+ *   out_dev : device, n_batch x 2^n_open complex128, ACCUMULATED (+=) in FP64, slices in
+ *             ascending order, so disjoint slice ranges compose.
+ * Errors: QF_ERR_ARG (range), QF_ERR_WORKSPACE, QF_ERR_HIP, QF_ERR_INJECTED. */
+qf_status qf_amplitudes(qf_plan* plan, int n_batch, const uint8_t* bits_dev, int64_t s_begin,
+                        int64_t s_end, double* out_dev);
+
+/* --- kernel-level entry points (the steps of one contraction; used by tests and bench) --- */
+
+/* Permute ("T" of TTGT, Sec. III-E): dst[j] = scale * src[src_base + sum_i bit_i(j) * 2^perm[i]]
+ * for j in [0, 2^nbits), complex64.  perm[i] is the source bit position of destination bit i
+ * (bit 0 = least significant); positions must be distinct and < 63.  src and dst must not
+ * overlap. */
+qf_status qf_permute(qf_ctx* ctx, const void* src, void* dst, int nbits, const int32_t* perm,
+                     int64_t src_base, float scale);
+
+/* Complex GEMM ("G" of TTGT, Sec. III-E), batched:
+ *   C[b][m][n] = sum_k A[b][m][k] * B[b][n][k]      (no conjugation), complex64,
+ * A row-major M x K, B row-major N x K (both K-contiguous), C row-major M x N.
+ * Batch strides are in complex elements.  M, N, K >= 1.  precision: qf_precision. */
+qf_status qf_cgemm(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, const void* A,
+                   const void* B, void* C, int64_t batch, int64_t stride_a, int64_t stride_b,
+                   int64_t stride_c);
+
+/* Time one launch configuration of qf_cgemm / qf_permute with HIP events on the context's
+ * stream: runs `reps` launches and returns the average milliseconds per launch in *ms.
+ * Synchronises the stream. */
+qf_status qf_time_cgemm(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, const void* A,
+                        const void* B, void* C, int reps, float* ms);
+qf_status qf_time_permute(qf_ctx* ctx, const void* src, void* dst, int nbits, const int32_t* perm,
+                          int reps, float* ms);
+
+/* Event timing of the dominant kernel inside qf_amplitudes: total milliseconds and count of
+ * the largest-volume GEMM launches since the last reset (measured with HIP events on the
+ * context stream when enabled; enabling adds a stream synchronisation per such launch). */
+qf_status qf_profile_enable(qf_ctx* ctx, int enable);
+qf_status qf_profile_read(qf_ctx* ctx, double* gemm_ms, int64_t* gemm_launches, double* gemm_flops,
+                          int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QFMI_H */

@@ -143,3 +143,25 @@ def amplitudes(circ, bits: np.ndarray, plan: Optional[dict] = None, slices=None)
         for s in slices:
             out[bi] += slice_amplitudes(circ, bits[bi], plan, s, wl)
     return out
+
+
+def partial_contract(circ, bits_row: np.ndarray, plan: dict, s: int, n_steps: int):
+    """Run only the first n_steps contractions of slice s (used to time a bounded sample of a
+    large workload); returns the last intermediate and its labels."""
+    if isinstance(circ, str):
+        circ = read_circuit(circ)
+    n = circ.n
+    tens, labels = world_lines(circ)
+    open_q = list(plan.get("open", []))
+    cutv = _cut_values(plan.get("cuts", []), s)
+    nodes = []
+    for q in range(n):
+        bit = None if q in open_q else int(bits_row[q])
+        nodes.append(_leaf(tens[q], labels[q], q, bit, cutv))
+    last = None
+    for a, b in plan["steps"][:n_steps]:
+        (ta, la), (tb, lb) = nodes[a], nodes[b]
+        last = _contract(ta, la, tb, lb)
+        nodes.append(last)
+        nodes[a] = nodes[b] = None
+    return last

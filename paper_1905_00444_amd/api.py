@@ -1,0 +1,257 @@
+"""Python binding of the qFlex-style amplitude library (thin: marshalling only).
+
+Every step of the computation runs in the HIP kernels behind include/qfmi.h; PyTorch only
+provides device memory (the workspace, inputs and outputs) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, load
+from .gates import gate_entries, is_two_qubit
+
+PRECISIONS = {"fp32": _lib.QF_FP32, "bf16x3": _lib.QF_BF16X3, "fp16": _lib.QF_FP16}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """A device, a stream and a growable workspace (a torch uint8 buffer)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        check(self.lib.qf_ctx_create(device, C.c_void_p(self.stream.cuda_stream), None, 0, C.byref(h)))
+        self.h = h
+        self.ws = None
+
+    def ensure_workspace(self, nbytes: int) -> None:
+        torch = _torch()
+        nbytes = max(int(nbytes), 4096)
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = None
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            check(self.lib.qf_ctx_set_workspace(self.h, C.c_void_p(self.ws.data_ptr()), self.ws.numel()), self.h)
+
+    def synchronize(self) -> None:
+        self.stream.synchronize()
+
+    def close(self) -> None:
+        if self.h:
+            self.lib.qf_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def read_circuit_text(text: str):
+    """(rows, cols, removed, n, ops) with ops = [(cycle, name, qubits)] from the text format:
+    '# grid rows cols [r:c ...]', the qubit count, then '<cycle> <name> <q0> [<q1>]' lines."""
+    rows = cols = None
+    removed = []
+    n = None
+    ops = []
+    for raw in text.splitlines():
+        s = raw.strip()
+        if not s:
+            continue
+        if s.startswith("#"):
+            f = s[1:].split()
+            if f and f[0] == "grid":
+                rows, cols = int(f[1]), int(f[2])
+                removed = [tuple(int(v) for v in x.split(":")) for x in f[3:]]
+            continue
+        if n is None:
+            n = int(s)
+            continue
+        f = s.split()
+        ops.append((int(f[0]), f[1], tuple(int(v) for v in f[2:])))
+    if rows is None:
+        rows, cols = 1, n
+    return rows, cols, removed, n, ops
+
+
+class Circuit:
+    def __init__(self, ctx: Context, text: str):
+        self.ctx = ctx
+        self.text = text
+        rows, cols, removed, n, ops = read_circuit_text(text)
+        self.rows, self.cols, self.n = rows, cols, n
+        present = np.ones(rows * cols, dtype=np.uint8)
+        for r, c in removed:
+            present[r * cols + c] = 0
+        arr = (_lib.qf_op * len(ops))()
+        self.values = np.zeros((len(ops), 4), dtype=np.complex64)
+        for i, (cyc, name, qs) in enumerate(ops):
+            ent = gate_entries(name)
+            self.values[i] = ent
+            arr[i].cycle = cyc
+            if len(qs) == 1:
+                arr[i].kind, arr[i].q0, arr[i].q1 = _lib.QF_OP_1Q, qs[0], -1
+            else:
+                if not is_two_qubit(name):
+                    raise ValueError(f"{name} is not a diagonal two-qubit gate")
+                arr[i].kind, arr[i].q0, arr[i].q1 = _lib.QF_OP_2Q_DIAG, qs[0], qs[1]
+            for j in range(4):
+                arr[i].values[2 * j] = float(ent[j].real)
+                arr[i].values[2 * j + 1] = float(ent[j].imag)
+        self.ops = ops
+        self._present = present
+        h = C.c_void_p()
+        check(ctx.lib.qf_circuit_create(ctx.h, rows, cols, present.ctypes.data_as(C.c_void_p), len(ops), arr,
+                                        C.byref(h)), ctx.h)
+        self.h = h
+
+    def set_values(self, values: np.ndarray) -> None:
+        """values: (n_ops, 4) complex entries in op order."""
+        v = np.ascontiguousarray(np.asarray(values, dtype=np.complex64).reshape(-1, 4))
+        flat = v.view(np.float32).reshape(-1)
+        check(self.ctx.lib.qf_circuit_set_values(self.h, flat.ctypes.data_as(C.POINTER(C.c_float))), self.ctx.h)
+        self.values = v.copy()
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.ctx.lib.qf_circuit_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class Plan:
+    def __init__(self, ctx: Context, circuit: Circuit, plan: dict, precision: str = "fp32", hoist: bool = True):
+        self.ctx = ctx
+        self.circuit = circuit
+        self.plan = plan
+        self.precision = precision
+        steps = np.ascontiguousarray(np.asarray(plan["steps"], dtype=np.int32).reshape(-1))
+        cuts = plan.get("cuts", [])
+        carr = (_lib.qf_cut * max(1, len(cuts)))()
+        for i, (q0, q1, lo, nb) in enumerate(cuts):
+            carr[i].q0, carr[i].q1, carr[i].bit_lo, carr[i].nbits = q0, q1, lo, nb
+        opn = np.ascontiguousarray(np.asarray(plan.get("open", []), dtype=np.int32))
+        self._keep = (steps, carr, opn)
+        d = _lib.qf_plan_desc()
+        d.n_steps = len(steps) // 2
+        d.steps = steps.ctypes.data_as(C.POINTER(C.c_int32))
+        d.n_cuts = len(cuts)
+        d.cuts = carr
+        d.n_open = len(opn)
+        d.open = opn.ctypes.data_as(C.POINTER(C.c_int32)) if len(opn) else None
+        d.precision = PRECISIONS[precision]
+        d.flags = 0 if hoist else _lib.QF_PLAN_NO_HOIST
+        h = C.c_void_p()
+        check(ctx.lib.qf_plan_create(ctx.h, circuit.h, C.byref(d), C.byref(h)), ctx.h)
+        self.h = h
+        self.n_open = len(opn)
+
+    def info(self) -> dict:
+        inf = _lib.qf_plan_info()
+        check(self.ctx.lib.qf_plan_info_get(self.h, C.byref(inf)), self.ctx.h)
+        return {k: getattr(inf, k) for k, _ in _lib.qf_plan_info._fields_}
+
+    def flops(self, s_begin: int, s_end: int) -> float:
+        """Executed algorithmic flops for one bitstring over slices [s_begin, s_end)."""
+        f = C.c_double()
+        check(self.ctx.lib.qf_plan_flops(self.h, int(s_begin), int(s_end), C.byref(f)), self.ctx.h)
+        return f.value
+
+    def amplitudes(self, bits, s_begin: int = 0, s_end: Optional[int] = None, out=None):
+        """Amplitudes (n_batch, 2^n_open) complex128 on the device, summed over slices
+        [s_begin, s_end) and added into `out` if given."""
+        torch = _torch()
+        info = self.info()
+        if s_end is None:
+            s_end = info["n_slices"]
+        self.ctx.ensure_workspace(info["workspace_bytes"])
+        if isinstance(bits, np.ndarray):
+            bits_t = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint8)).to(self.ctx.device)
+        else:
+            bits_t = bits.to(device=self.ctx.device, dtype=torch.uint8).contiguous()
+        nb = bits_t.shape[0]
+        if out is None:
+            out = torch.zeros((nb, 2 ** self.n_open), dtype=torch.complex128, device=self.ctx.device)
+        with torch.cuda.stream(self.ctx.stream):
+            st = self.ctx.lib.qf_amplitudes(self.h, nb, C.c_void_p(bits_t.data_ptr()), int(s_begin), int(s_end),
+                                            C.c_void_p(out.data_ptr()))
+        self._bits_keepalive = bits_t
+        check(st, self.ctx.h)
+        return out
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.ctx.lib.qf_plan_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+# --- kernel-level calls --------------------------------------------------------------------
+
+def permute(ctx: Context, src, dst, perm: Sequence[int], base: int = 0, scale: float = 1.0) -> None:
+    p = np.ascontiguousarray(np.asarray(perm, dtype=np.int32))
+    check(ctx.lib.qf_permute(ctx.h, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), len(p),
+                             p.ctypes.data_as(C.POINTER(C.c_int32)), int(base), float(scale)), ctx.h)
+
+
+def cgemm(ctx: Context, A, B, precision: str = "fp32", out=None):
+    """C[m, n] = sum_k A[m, k] B[n, k] (complex64, no conjugation)."""
+    torch = _torch()
+    M, K = A.shape
+    N, K2 = B.shape
+    assert K == K2 and A.dtype == torch.complex64 and B.dtype == torch.complex64
+    A = A.contiguous()
+    B = B.contiguous()
+    if out is None:
+        out = torch.empty((M, N), dtype=torch.complex64, device=A.device)
+    if precision == "fp16":
+        ctx.ensure_workspace(4096)
+    check(ctx.lib.qf_cgemm(ctx.h, PRECISIONS[precision], M, N, K, C.c_void_p(A.data_ptr()),
+                           C.c_void_p(B.data_ptr()), C.c_void_p(out.data_ptr()), 1, 0, 0, 0), ctx.h)
+    return out
+
+
+def time_cgemm(ctx: Context, A, B, C_out, precision: str, reps: int = 5) -> float:
+    M, K = A.shape
+    N = B.shape[0]
+    ms = C.c_float()
+    if precision == "fp16":
+        ctx.ensure_workspace(4096)
+    check(ctx.lib.qf_time_cgemm(ctx.h, PRECISIONS[precision], M, N, K, C.c_void_p(A.data_ptr()),
+                                C.c_void_p(B.data_ptr()), C.c_void_p(C_out.data_ptr()), reps, C.byref(ms)), ctx.h)
+    return ms.value
+
+
+def time_permute(ctx: Context, src, dst, perm: Sequence[int], reps: int = 5) -> float:
+    p = np.ascontiguousarray(np.asarray(perm, dtype=np.int32))
+    ms = C.c_float()
+    check(ctx.lib.qf_time_permute(ctx.h, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), len(p),
+                                  p.ctypes.data_as(C.POINTER(C.c_int32)), reps, C.byref(ms)), ctx.h)
+    return ms.value
+
+
+def profile_enable(ctx: Context, on: bool = True) -> None:
+    check(ctx.lib.qf_profile_enable(ctx.h, 1 if on else 0), ctx.h)
+
+
+def profile_read(ctx: Context, reset: bool = True):
+    ms = C.c_double()
+    n = C.c_int64()
+    fl = C.c_double()
+    check(ctx.lib.qf_profile_read(ctx.h, C.byref(ms), C.byref(n), C.byref(fl), 1 if reset else 0), ctx.h)
+    return ms.value, n.value, fl.value

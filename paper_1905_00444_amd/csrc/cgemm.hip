@@ -1,0 +1,366 @@
+// Complex GEMM, the "G" of the transpose-GEMM-transpose contraction (paper Sec. III-E):
+//   C[m][n] = sum_k A[m][k] * B[n][k]   (complex64 in HBM; A and B both K-contiguous).
+//
+// The paper runs complex FP32 CGEMM on V100 CUDA cores.  On gfx950 the products run on MFMA
+// through the real embedding of complex multiplication: with A viewed as a real M x 2K matrix
+// (re, im interleaved, exactly its complex64 memory layout) and B expanded to a real 2K x 2N
+// matrix whose 2x2 blocks are [[br, bi], [-bi, br]], the real product is C as a real M x 2N
+// matrix, again (re, im) interleaved.  The expansion is never stored: each lane builds its
+// B operand from the complex values in LDS by negating or swapping halves.  The algorithmic
+// count 8 M N K of the paper's formula F = 8 sqrt(v0 v1 v2) equals the real MFMA work.
+//
+// Precisions (the operand conversion happens when a K-tile is staged into LDS):
+//   FP32   : v_mfma_f32_16x16x4_f32 on the FP32 operands.
+//   BF16X3 : x = hi + lo with hi = bf16(x), lo = bf16(x - hi); C += hi*hi + hi*lo + lo*hi on
+//            v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the lo*lo term, about 2^-16
+//            relative, is dropped).
+//   FP16   : x * 2^s rounded to fp16 with s chosen from the operand's max magnitude so the
+//            largest entry lands near 2^14; v_mfma_f32_16x16x32_f16, FP32 accumulation; the
+//            epilogue multiplies by 2^-(sA+sB), which is exact (paper Sec. III-E: normalise the
+//            inputs, renormalise at the end).
+//
+// Tiling: 256 threads = 4 waves as 2 x 2; a wave owns WTM x WTN MFMA tiles of 16 rows x 16 real
+// columns (8 complex); block tile BM = 32 WTM rows x BN = 16 WTN complex columns; K-tiles of
+// 32 complex.  Global loads for the next K-tile are issued into registers before the current
+// tile's MFMAs, then converted and stored to LDS.  Rows are padded by 16 bytes in LDS.
+// Workgroups are remapped so consecutive tiles share an XCD (8 XCDs, round-robin dispatch)
+// and rasterised in groups of row-tiles for L2 reuse.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "qf_kernels.h"
+
+namespace qf {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+enum { P_FP32 = 0, P_BF16X3 = 1, P_FP16 = 2 };
+
+constexpr int kBK = 32;          // complex k per K-tile
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float re, float im) {
+  __bf16 a = (__bf16)re, b = (__bf16)im;
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+__device__ __forceinline__ float bf16_lo_to_f32(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi_to_f32(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ uint32_t pack_f16x2(float re, float im) {
+  _Float16 a = (_Float16)re, b = (_Float16)im;
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+// Scale exponent that brings max|x| to about 2^14 (FP16 max is 65504 ~ 2^16).
+__device__ __forceinline__ int fp16_shift(const uint32_t* amax) {
+  if (!amax) return 0;
+  const float m = __uint_as_float(*amax);
+  if (!(m > 0.f)) return 0;
+  int e;
+  frexpf(m, &e);  // m = f * 2^e, f in [0.5, 1)
+  return 14 - e;
+}
+
+template <int PREC>
+struct LdsRow;  // bytes per complex element in LDS per plane
+template <> struct LdsRow<P_FP32> { static constexpr int elem = 8, planes = 1; };
+template <> struct LdsRow<P_BF16X3> { static constexpr int elem = 4, planes = 2; };
+template <> struct LdsRow<P_FP16> { static constexpr int elem = 4, planes = 1; };
+
+template <int PREC, int ROWS>
+struct TileLds {
+  static constexpr int row_bytes = kBK * LdsRow<PREC>::elem + 16;
+  static constexpr int plane_bytes = ROWS * row_bytes;
+  static constexpr int bytes = plane_bytes * LdsRow<PREC>::planes;
+};
+
+// Stage ROWS x 32 complex (held as float4 = 2 complex per register) into LDS with conversion.
+template <int PREC, int ROWS>
+__device__ __forceinline__ void stage_tile(char* lds, const float4 (&r)[ROWS * 16 / kThreads], float scale) {
+  constexpr int per = ROWS * 16 / kThreads;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    const int idx = tid + i * kThreads;
+    const int row = idx >> 4, c4 = idx & 15;  // c4: pair of complex k = 2*c4, 2*c4+1
+    const float4 v = r[i];
+    if constexpr (PREC == P_FP32) {
+      *reinterpret_cast<float4*>(lds + row * TileLds<PREC, ROWS>::row_bytes + c4 * 16) = v;
+    } else if constexpr (PREC == P_BF16X3) {
+      const uint32_t h0 = pack_bf16x2(v.x, v.y), h1 = pack_bf16x2(v.z, v.w);
+      const uint32_t l0 = pack_bf16x2(v.x - bf16_lo_to_f32(h0), v.y - bf16_hi_to_f32(h0));
+      const uint32_t l1 = pack_bf16x2(v.z - bf16_lo_to_f32(h1), v.w - bf16_hi_to_f32(h1));
+      char* base = lds + row * TileLds<PREC, ROWS>::row_bytes + c4 * 8;
+      *reinterpret_cast<uint2*>(base) = make_uint2(h0, h1);
+      *reinterpret_cast<uint2*>(base + TileLds<PREC, ROWS>::plane_bytes) = make_uint2(l0, l1);
+    } else {
+      const uint32_t h0 = pack_f16x2(v.x * scale, v.y * scale), h1 = pack_f16x2(v.z * scale, v.w * scale);
+      *reinterpret_cast<uint2*>(lds + row * TileLds<PREC, ROWS>::row_bytes + c4 * 8) = make_uint2(h0, h1);
+    }
+  }
+}
+
+template <int ROWS>
+__device__ __forceinline__ void load_tile(float4 (&r)[ROWS * 16 / kThreads], const float2* __restrict__ p,
+                                          int64_t ld, int64_t k0) {
+  constexpr int per = ROWS * 16 / kThreads;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    const int idx = tid + i * kThreads;
+    const int row = idx >> 4, c4 = idx & 15;
+    r[i] = *reinterpret_cast<const float4*>(p + row * ld + k0 + 2 * c4);
+  }
+}
+
+// B operand for real column (n, q): q = 0 -> (br, -bi), q = 1 -> (bi, br), per packed complex.
+__device__ __forceinline__ uint32_t bexpand16(uint32_t w, int q) {
+  return q ? ((w >> 16) | (w << 16)) : (w ^ 0x80000000u);
+}
+
+template <int PREC, int WTM, int WTN>
+__global__ void __launch_bounds__(kThreads)
+cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
+           float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, const uint32_t* amaxA,
+           const uint32_t* amaxB) {
+  constexpr int BM = 32 * WTM, BN = 16 * WTN;
+  using LA = TileLds<PREC, BM>;
+  using LB = TileLds<PREC, BN>;
+  __shared__ __attribute__((aligned(16))) char lds[LA::bytes + LB::bytes];
+  char* ldsA = lds;
+  char* ldsB = lds + LA::bytes;
+
+  // tile mapping: XCD-contiguous remap, then grouped rasterisation over row tiles
+  const int64_t tiles_m = M / BM, tiles_n = N / BN;
+  const int64_t ntiles = tiles_m * tiles_n;
+  int64_t bid = blockIdx.x;
+  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  const int64_t group = 8;
+  const int64_t per_group = group * tiles_n;
+  const int64_t gidx = bid / per_group;
+  const int64_t first_m = gidx * group;
+  const int64_t gsize = (tiles_m - first_m) < group ? (tiles_m - first_m) : group;
+  const int64_t tm = first_m + (bid % per_group) % gsize;
+  const int64_t tn = (bid % per_group) / gsize;
+
+  const int64_t batch = blockIdx.z;
+  A += batch * sa + tm * BM * K;
+  B += batch * sb + tn * BN * K;
+  C += batch * sc;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * (16 * WTM);   // wave's first row in the block tile
+  const int wc = (wave & 1) * (8 * WTN);     // wave's first complex column
+  const int l16 = lane & 15, lg = lane >> 4;
+
+  float scale_a = 1.f, scale_b = 1.f, unscale = 1.f;
+  if constexpr (PREC == P_FP16) {
+    const int s_a = fp16_shift(amaxA), s_b = fp16_shift(amaxB);
+    scale_a = ldexpf(1.f, s_a);
+    scale_b = ldexpf(1.f, s_b);
+    unscale = ldexpf(1.f, -(s_a + s_b));
+  }
+
+  f4 acc[WTM][WTN];
+#pragma unroll
+  for (int i = 0; i < WTM; ++i)
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+
+  float4 ra[BM * 16 / kThreads], rb[BN * 16 / kThreads];
+  load_tile<BM>(ra, A, K, 0);
+  load_tile<BN>(rb, B, K, 0);
+  const int64_t nk = K / kBK;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    stage_tile<PREC, BM>(ldsA, ra, scale_a);
+    stage_tile<PREC, BN>(ldsB, rb, scale_b);
+    __syncthreads();
+    if (kt + 1 < nk) {
+      load_tile<BM>(ra, A, K, (kt + 1) * kBK);
+      load_tile<BN>(rb, B, K, (kt + 1) * kBK);
+    }
+    if constexpr (PREC == P_FP32) {
+      // 16 chunks of 2 complex k; lane group lg holds real k = lg: complex kc = lg >> 1, part = lg & 1
+      const int kc_l = lg >> 1, part = lg & 1;
+      const int q = l16 & 1;
+#pragma unroll 4
+      for (int c = 0; c < kBK / 2; ++c) {
+        float a[WTM];
+#pragma unroll
+        for (int i = 0; i < WTM; ++i) {
+          const float* p = reinterpret_cast<const float*>(ldsA + (wr + 16 * i + l16) * LA::row_bytes) + 2 * (2 * c + kc_l);
+          a[i] = p[part];
+        }
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+          const float* p = reinterpret_cast<const float*>(ldsB + (wc + 8 * j + (l16 >> 1)) * LB::row_bytes) + 2 * (2 * c + kc_l);
+          const float br = p[0], bi = p[1];
+          const float b = q ? (part ? br : bi) : (part ? -bi : br);
+#pragma unroll
+          for (int i = 0; i < WTM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b, acc[i][j], 0, 0, 0);
+        }
+      }
+    } else {
+      // 2 chunks of 16 complex k; lane group lg holds complex k 4*lg .. 4*lg+3 (8 real k)
+      const int q = l16 & 1;
+#pragma unroll
+      for (int c = 0; c < kBK / 16; ++c) {
+        u4 ah[WTM], al[WTM];
+#pragma unroll
+        for (int i = 0; i < WTM; ++i) {
+          const char* p = ldsA + (wr + 16 * i + l16) * LA::row_bytes + (16 * c + 4 * lg) * 4;
+          ah[i] = *reinterpret_cast<const u4*>(p);
+          if constexpr (PREC == P_BF16X3) al[i] = *reinterpret_cast<const u4*>(p + LA::plane_bytes);
+        }
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+          const char* p = ldsB + (wc + 8 * j + (l16 >> 1)) * LB::row_bytes + (16 * c + 4 * lg) * 4;
+          u4 bh = *reinterpret_cast<const u4*>(p);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) bh[e] = bexpand16(bh[e], q);
+          if constexpr (PREC == P_BF16X3) {
+            u4 bl = *reinterpret_cast<const u4*>(p + LB::plane_bytes);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bl[e] = bexpand16(bl[e], q);
+            const bf8 vbh = __builtin_bit_cast(bf8, bh), vbl = __builtin_bit_cast(bf8, bl);
+#pragma unroll
+            for (int i = 0; i < WTM; ++i)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, al[i]), vbh, acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < WTM; ++i)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), vbl, acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < WTM; ++i)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), vbh, acc[i][j], 0, 0, 0);
+          } else {
+            const h8 vb = __builtin_bit_cast(h8, bh);
+#pragma unroll
+            for (int i = 0; i < WTM; ++i)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, ah[i]), vb, acc[i][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // Epilogue: lane holds real column (n, q = l16 & 1) for rows 4*lg .. 4*lg+3 of each tile.
+  // Exchange with the partner lane (l ^ 1) so each lane owns two complex results.
+  const int q = l16 & 1;
+#pragma unroll
+  for (int i = 0; i < WTM; ++i)
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+      const f4 v = acc[i][j] * unscale;
+      const float s0 = q ? v[0] : v[2], s1 = q ? v[1] : v[3];
+      const float r0 = __shfl_xor(s0, 1), r1 = __shfl_xor(s1, 1);
+      const int64_t row = tm * BM + wr + 16 * i + 4 * lg + (q ? 2 : 0);
+      const int64_t col = tn * BN + wc + 8 * j + (l16 >> 1);
+      float2 o0, o1;
+      if (q) { o0 = make_float2(r0, v[2]); o1 = make_float2(r1, v[3]); }
+      else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
+      C[row * N + col] = o0;
+      C[(row + 1) * N + col] = o1;
+    }
+}
+
+// Small or thin shapes: one thread per output element, FP32 complex FMA over K.
+__global__ void __launch_bounds__(256)
+cgemm_simt(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
+           float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc) {
+  const int64_t batch = blockIdx.z;
+  A += batch * sa;
+  B += batch * sb;
+  C += batch * sc;
+  const int64_t total = M * N;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = idx / N, n = idx - m * N;
+    const float2* a = A + m * K;
+    const float2* b = B + n * K;
+    float cr = 0.f, ci = 0.f;
+    for (int64_t k = 0; k < K; ++k) {
+      const float2 x = a[k], y = b[k];
+      cr = fmaf(x.x, y.x, cr);
+      cr = fmaf(-x.y, y.y, cr);
+      ci = fmaf(x.x, y.y, ci);
+      ci = fmaf(x.y, y.x, ci);
+    }
+    C[m * N + n] = make_float2(cr, ci);
+  }
+}
+
+template <int PREC, int WTM, int WTN>
+static hipError_t launch_tiled(hipStream_t st, int64_t M, int64_t N, int64_t K, const float2* A,
+                               const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb,
+                               int64_t sc, const uint32_t* amaxA, const uint32_t* amaxB) {
+  constexpr int BM = 32 * WTM, BN = 16 * WTN;
+  const int64_t tiles = (M / BM) * (N / BN);
+  hipLaunchKernelGGL((cgemm_mfma<PREC, WTM, WTN>), dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kThreads), 0, st,
+                     M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB);
+  return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t dispatch(hipStream_t st, int64_t M, int64_t N, int64_t K, const float2* A, const float2* B,
+                           float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
+                           const uint32_t* amaxA, const uint32_t* amaxB) {
+  if (M >= 128 && N >= 64) return launch_tiled<PREC, 4, 4>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
+  if (M >= 64 && N >= 32) return launch_tiled<PREC, 2, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
+  return launch_tiled<PREC, 1, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
+}
+
+static bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
+                           const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
+                           const uint32_t* amaxA, const uint32_t* amaxB) {
+  const bool tiled = pow2(M) && pow2(N) && pow2(K) && M >= 32 && N >= 32 && K >= kBK;
+  if (!tiled) {
+    const int64_t total = M * N;
+    unsigned blocks = (unsigned)((total + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(cgemm_simt, dim3(blocks, 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C, sa, sb, sc);
+    return hipGetLastError();
+  }
+  switch (precision) {
+    case P_FP32: return dispatch<P_FP32>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
+    case P_BF16X3: return dispatch<P_BF16X3>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
+    case P_FP16: return dispatch<P_FP16>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_cgemm(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
+                        const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc) {
+  return launch_cgemm_ex(st, precision, M, N, K, A, B, C, batch, sa, sb, sc, nullptr, nullptr);
+}
+
+// Max |re|, |im| of a complex64 array into *amax (as float bits; non-negative floats order
+// like their bit patterns).  *amax must be zero before the launch.
+__global__ void __launch_bounds__(256)
+amax_kernel(const float2* __restrict__ x, int64_t n, uint32_t* amax) {
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float2 v = x[i];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(m));
+}
+
+__global__ void zero_u32(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_amax(hipStream_t st, const float2* x, int64_t n, uint32_t* amax) {
+  hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, amax, 1);
+  unsigned blocks = (unsigned)((n + 255) / 256);
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(amax_kernel, dim3(blocks), dim3(256), 0, st, x, n, amax);
+  return hipGetLastError();
+}
+
+} // namespace qf

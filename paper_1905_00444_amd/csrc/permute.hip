@@ -1,0 +1,119 @@
+// Tensor permute, the "T" of the transpose-GEMM-transpose contraction (paper Sec. III-E).
+//
+// Every index of the network has dimension 2, so a tensor of volume 2^b is addressed by b bits
+// and any index permutation is a permutation of address bits.  The kernel computes
+//   dst[j] = scale * src[src_base + sum_i bit_i(j) << perm[i]],   j < 2^b,
+// i.e. a bit-permuting gather; fixed source bits (a bitstring's output bit, a slice's cut bits)
+// are folded into src_base, so the same kernel also extracts a slice of a world-line tensor.
+//
+// HBM-bound design for gfx950: a workgroup moves one tile of 2^t elements whose bits are the
+// union of the r lowest-source-position bits (reads sweep contiguous source runs) and the w
+// lowest destination bits (writes sweep contiguous destination runs).  The tile is staged in
+// LDS: read in source order, written out in destination order.  The remaining ("outer") bits
+// enumerate the tiles.  Rows of 32 elements are padded by one element in LDS so that the
+// destination-order reads, which stride through the source order, spread over the banks.
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <vector>
+#include "qf_kernels.h"
+
+namespace qf {
+
+constexpr int kPermThreads = 256;
+constexpr int kPermMaxTile = 11;
+
+struct PermKernelArgs {
+  int t;                    // tile bits
+  int n_outer;              // outer bits
+  int u_src[kPermMaxTile];  // source bit position of read-order tile bit i
+  int v_dst[kPermMaxTile];  // destination bit of write-order tile bit i
+  int v_to_u[kPermMaxTile]; // read-order index of write-order tile bit i
+  int o_src[64];            // source bit position of outer bit i
+  int o_dst[64];            // destination bit of outer bit i
+  int64_t src_base;
+  float scale;
+  const uint8_t* dyn_bits;
+  int64_t dyn_stride;
+};
+
+__device__ __forceinline__ int lds_index(int u) { return u + (u >> 5); }
+
+__global__ void __launch_bounds__(kPermThreads)
+permute_kernel(const float2* __restrict__ src, float2* __restrict__ dst, PermKernelArgs a) {
+  extern __shared__ float2 tile[];
+  const int64_t g = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+  int64_t sbase = a.src_base, dbase = 0;
+  if (a.dyn_bits) sbase += (int64_t)(a.dyn_bits[0] & 1) * a.dyn_stride;
+  for (int i = 0; i < a.n_outer; ++i) {
+    const int64_t bit = (g >> i) & 1;
+    sbase += bit << a.o_src[i];
+    dbase += bit << a.o_dst[i];
+  }
+  const int tvol = 1 << a.t;
+  for (int u = threadIdx.x; u < tvol; u += kPermThreads) {
+    int64_t off = 0;
+#pragma unroll
+    for (int i = 0; i < kPermMaxTile; ++i)
+      if (i < a.t) off |= (int64_t)((u >> i) & 1) << a.u_src[i];
+    tile[lds_index(u)] = src[sbase + off];
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < tvol; v += kPermThreads) {
+    int u = 0;
+    int64_t off = 0;
+#pragma unroll
+    for (int i = 0; i < kPermMaxTile; ++i)
+      if (i < a.t) {
+        const int bit = (v >> i) & 1;
+        u |= bit << a.v_to_u[i];
+        off |= (int64_t)bit << a.v_dst[i];
+      }
+    float2 x = tile[lds_index(u)];
+    x.x *= a.scale;
+    x.y *= a.scale;
+    dst[dbase + off] = x;
+  }
+}
+
+hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& p) {
+  const int b = p.nbits;
+  // destination bits sorted by source position
+  std::vector<int> by_src(b);
+  for (int i = 0; i < b; ++i) by_src[i] = i;
+  std::sort(by_src.begin(), by_src.end(), [&](int x, int y) { return p.perm[x] < p.perm[y]; });
+  const int target = std::min(b, kPermMaxTile);
+  const int r = std::min(b, 5), w = std::min(b, 5);
+  std::vector<char> in_tile(b, 0);
+  int t = 0;
+  for (int i = 0; i < r; ++i) if (!in_tile[by_src[i]]) { in_tile[by_src[i]] = 1; ++t; }
+  for (int i = 0; i < w && t < target; ++i) if (!in_tile[i]) { in_tile[i] = 1; ++t; }
+  for (int i = 0; i < b && t < target; ++i) if (!in_tile[by_src[i]]) { in_tile[by_src[i]] = 1; ++t; }
+  PermKernelArgs a = {};
+  a.t = t;
+  // read order: tile bits by ascending source position
+  std::vector<int> uorder;
+  for (int i = 0; i < b; ++i) if (in_tile[by_src[i]]) uorder.push_back(by_src[i]);
+  std::vector<int> vorder;
+  for (int i = 0; i < b; ++i) if (in_tile[i]) vorder.push_back(i);
+  for (int i = 0; i < t; ++i) {
+    a.u_src[i] = p.perm[uorder[i]];
+    a.v_dst[i] = vorder[i];
+    a.v_to_u[i] = (int)(std::find(uorder.begin(), uorder.end(), vorder[i]) - uorder.begin());
+  }
+  int no = 0;
+  for (int i = 0; i < b; ++i)
+    if (!in_tile[i]) { a.o_src[no] = p.perm[i]; a.o_dst[no] = i; ++no; }
+  a.n_outer = no;
+  a.src_base = p.src_base;
+  a.scale = p.scale;
+  a.dyn_bits = p.dyn_bits;
+  a.dyn_stride = p.dyn_stride;
+  const int64_t tiles = (int64_t)1 << no;
+  const unsigned gx = (unsigned)std::min<int64_t>(tiles, 65536);
+  const unsigned gy = (unsigned)(tiles / gx);
+  const size_t lds = (size_t)((1 << t) + (1 << t) / 32 + 1) * sizeof(float2);
+  hipLaunchKernelGGL(permute_kernel, dim3(gx, gy), dim3(kPermThreads), lds, st, src, dst, a);
+  return hipGetLastError();
+}
+
+} // namespace qf

@@ -1,0 +1,868 @@
+// Host runtime of the qFlex-style contraction library: the C-ABI of include/qfmi.h.
+//
+// Responsibilities (all on the host; every arithmetic step runs in the HIP kernels):
+//   * circuit -> grid bonds and world-line programs (paper Sec. III, time-first contraction);
+//   * plan validation, index ("label") bookkeeping of every tensor, cut bits (Sec. III-A),
+//     open output qubits (Sec. III-B);
+//   * TTGT layout choice per contraction (Sec. III-E): which operand plays A or B, the order
+//     of the contracted bits, and which operands need a permute;
+//   * workspace arena: persistent tensors (world-lines, subtrees reused across slices) and
+//     transients packed by lifetime; the library never allocates device memory (the paper's
+//     pre-allocated buffers with their own allocators, Sec. III-E, become one caller-owned
+//     workspace with offsets fixed at plan time);
+//   * the slice loop: a step is recomputed only when the bitstring or a cut value it depends
+//     on changes, and every slice's root is added into the FP64 output in ascending order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qfmi.h"
+#include "qf_kernels.h"
+
+namespace qf {
+hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
+                           const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
+                           const uint32_t* amaxA, const uint32_t* amaxB);
+hipError_t launch_amax(hipStream_t st, const float2* x, int64_t n, uint32_t* amax);
+}  // namespace qf
+
+using namespace qf;
+
+static const size_t kCtxScratch = 4096;  // start of the workspace reserved for small slots
+static const size_t kAlign = 256;
+
+static size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct qf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err;
+  const qf_plan* last_built = nullptr;
+  // profiling of the dominant GEMM class
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used;
+  double prof_flops = 0.0;
+  int64_t prof_launches = 0;
+};
+
+struct qf_circuit {
+  qf_ctx* ctx = nullptr;
+  int rows = 0, cols = 0, n = 0;
+  std::vector<qf_op> ops;  // sorted by (cycle, input order)
+  std::vector<int> order;  // ops[i] is input op order[i]
+  int64_t version = 0;
+};
+
+namespace {
+
+struct Node {
+  std::vector<int> labels;  // most significant first
+  bool leaf = false;
+  int qubit = -1;           // leaves
+  bool dep_bits = false;    // depends on the bitstring
+  uint64_t dep_cuts = 0;    // bit c: depends on cut c's value
+  bool persistent = false;
+  size_t offset = 0;        // arena byte offset of the dense result (intermediates)
+  int consumer = -1;        // step index that uses it
+};
+
+struct Operand {
+  int node = -1;
+  bool permute = false;
+  std::vector<int> perm;  // dst bit i <- src bit perm[i]
+  int nbits = 0;
+  size_t buf = 0;         // arena offset of the permuted copy
+};
+
+struct Step {
+  int l = -1, r = -1;
+  Operand A, B;           // roles after the swap (A has the larger free volume)
+  int m_bits = 0, n_bits = 0, k_bits = 0;
+  double flops = 0.0;
+  size_t out = 0;         // arena offset of the result
+};
+
+struct Buf {
+  size_t bytes;
+  int start, end;  // inclusive step range of the lifetime
+  size_t* where;
+};
+
+}  // namespace
+
+struct qf_plan {
+  qf_ctx* ctx = nullptr;
+  qf_circuit* circ = nullptr;
+  int n = 0;
+  int precision = 0;
+  int flags = 0;
+  std::vector<int> open;
+  std::vector<qf_cut> cuts;
+  std::vector<int> cut_offset;        // bit offset of each cut inside the slice id
+  int total_cut_bits = 0;
+  // labels
+  std::map<std::pair<int, int>, int> edge_index;
+  std::vector<int> edge_label_base, edge_nbits;
+  int n_bond_labels = 0;
+  std::vector<int> label_cut;          // per bond label: cut index or -1
+  std::vector<int> label_cut_shift;    // shift of the label's bit inside the slice id
+  // world-lines
+  std::vector<WlQubit> wl_qubits;
+  std::vector<WlInstr> wl_prog;
+  std::vector<std::vector<int>> leaf_full_labels;  // [X(q), bond labels in time order]
+  int max_nbond = 0;
+  // graph
+  std::vector<Node> nodes;
+  std::vector<Step> steps;
+  std::vector<int> root_pos;  // bit position in the root of open qubit t's output bit, t = MSB first
+  int peak_bits = 0;
+  double flops_per_slice = 0.0, flops_hoisted = 0.0, permute_bytes = 0.0;
+  double max_step_flops = 0.0;
+  // arena (offsets relative to the workspace start)
+  size_t off_gates = 0, off_wlq = 0, off_prog = 0, off_wl = 0, arena_end = 0;
+  std::vector<float2> gates_host;
+  int64_t built_version = -1;
+};
+
+// ---------------------------------------------------------------------------------------------
+static qf_status fail(qf_ctx* ctx, qf_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+static qf_status hip_fail(qf_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, QF_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define QF_HIP(ctx, expr)                                   \
+  do {                                                      \
+    hipError_t e__ = (expr);                                \
+    if (e__ != hipSuccess) return hip_fail(ctx, e__, #expr); \
+  } while (0)
+
+extern "C" {
+
+qf_status qf_ctx_create(int device, void* hip_stream, void* workspace, size_t ws_bytes, qf_ctx** out) {
+  if (!out) return QF_ERR_ARG;
+  *out = nullptr;
+  if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return QF_ERR_ARG;
+  qf_ctx* c = new (std::nothrow) qf_ctx();
+  if (!c) return QF_ERR_ARG;
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->ws = reinterpret_cast<char*>(workspace);
+  c->ws_bytes = workspace ? ws_bytes : 0;
+  *out = c;
+  return QF_OK;
+}
+
+qf_status qf_ctx_set_workspace(qf_ctx* ctx, void* workspace, size_t ws_bytes) {
+  if (!ctx) return QF_ERR_ARG;
+  if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return fail(ctx, QF_ERR_ARG, "workspace must be 256-byte aligned");
+  ctx->ws = reinterpret_cast<char*>(workspace);
+  ctx->ws_bytes = workspace ? ws_bytes : 0;
+  ctx->last_built = nullptr;
+  return QF_OK;
+}
+
+qf_status qf_ctx_set_stream(qf_ctx* ctx, void* hip_stream) {
+  if (!ctx) return QF_ERR_ARG;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return QF_OK;
+}
+
+void qf_ctx_destroy(qf_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& p : ctx->ev_used) { ctx->ev_pool.push_back(p.first); ctx->ev_pool.push_back(p.second); }
+  for (auto e : ctx->ev_pool) hipEventDestroy(e);
+  delete ctx;
+}
+
+const char* qf_last_error(const qf_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+// ---------------------------------------------------------------------------------------------
+qf_status qf_circuit_create(qf_ctx* ctx, int rows, int cols, const uint8_t* present, int n_ops, const qf_op* ops,
+                            qf_circuit** out) {
+  if (!ctx || !out || rows <= 0 || cols <= 0 || n_ops < 0 || (n_ops > 0 && !ops))
+    return fail(ctx, QF_ERR_ARG, "qf_circuit_create: bad arguments");
+  *out = nullptr;
+  std::vector<int> site_of;  // qubit -> r*cols + c
+  for (int s = 0; s < rows * cols; ++s)
+    if (!present || present[s]) site_of.push_back(s);
+  const int n = (int)site_of.size();
+  if (n < 2) return fail(ctx, QF_ERR_UNSUPPORTED, "circuits need at least 2 qubits");
+  for (int i = 0; i < n_ops; ++i) {
+    const qf_op& o = ops[i];
+    if (o.kind == QF_OP_1Q) {
+      if (o.q0 < 0 || o.q0 >= n) return fail(ctx, QF_ERR_ARG, "op " + std::to_string(i) + ": qubit out of range");
+    } else if (o.kind == QF_OP_2Q_DIAG) {
+      if (o.q0 < 0 || o.q1 < 0 || o.q0 >= n || o.q1 >= n || o.q0 >= o.q1)
+        return fail(ctx, QF_ERR_ARG, "op " + std::to_string(i) + ": two-qubit gate needs 0 <= q0 < q1 < n");
+      const int s0 = site_of[o.q0], s1 = site_of[o.q1];
+      const int r0 = s0 / cols, c0 = s0 % cols, r1 = s1 / cols, c1 = s1 % cols;
+      if (std::abs(r0 - r1) + std::abs(c0 - c1) != 1)
+        return fail(ctx, QF_ERR_ARG, "op " + std::to_string(i) + ": qubits are not grid neighbours");
+    } else {
+      return fail(ctx, QF_ERR_ARG, "op " + std::to_string(i) + ": unknown kind");
+    }
+  }
+  qf_circuit* c = new (std::nothrow) qf_circuit();
+  if (!c) return fail(ctx, QF_ERR_ARG, "out of host memory");
+  c->ctx = ctx;
+  c->rows = rows;
+  c->cols = cols;
+  c->n = n;
+  c->order.resize(n_ops);
+  for (int i = 0; i < n_ops; ++i) c->order[i] = i;
+  std::stable_sort(c->order.begin(), c->order.end(), [&](int a, int b) { return ops[a].cycle < ops[b].cycle; });
+  c->ops.resize(n_ops);
+  for (int i = 0; i < n_ops; ++i) c->ops[i] = ops[c->order[i]];
+  *out = c;
+  return QF_OK;
+}
+
+qf_status qf_circuit_set_values(qf_circuit* circ, const float* values) {
+  if (!circ || !values) return QF_ERR_ARG;
+  for (size_t i = 0; i < circ->ops.size(); ++i)
+    std::memcpy(circ->ops[i].values, values + 8 * (size_t)circ->order[i], 8 * sizeof(float));
+  ++circ->version;
+  return QF_OK;
+}
+
+void qf_circuit_destroy(qf_circuit* circ) { delete circ; }
+
+// ---------------------------------------------------------------------------------------------
+static bool contains(const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); }
+
+// perm for gathering `want` (label order, MSB first) out of a source with label order `have`
+static std::vector<int> make_perm(const std::vector<int>& have, const std::vector<int>& want) {
+  const int b = (int)want.size(), hb = (int)have.size();
+  std::vector<int> perm(b);
+  for (int i = 0; i < b; ++i) {
+    const int lab = want[b - 1 - i];
+    const int j = (int)(std::find(have.begin(), have.end(), lab) - have.begin());
+    perm[i] = hb - 1 - j;
+  }
+  return perm;
+}
+
+static bool is_identity(const std::vector<int>& perm) {
+  for (size_t i = 0; i < perm.size(); ++i)
+    if (perm[i] != (int)i) return false;
+  return true;
+}
+
+qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, qf_plan** out) {
+  if (!ctx || !circ || !d || !out) return fail(ctx, QF_ERR_ARG, "qf_plan_create: null argument");
+  *out = nullptr;
+  if (d->precision < QF_FP32 || d->precision > QF_FP16) return fail(ctx, QF_ERR_ARG, "unknown precision");
+  const int n = circ->n;
+  std::unique_ptr<qf_plan> p(new qf_plan());
+  p->ctx = ctx;
+  p->circ = circ;
+  p->n = n;
+  p->precision = d->precision;
+  p->flags = d->flags;
+
+  // ---- bonds: one bit per diagonal two-qubit gate, time order (ops are sorted by cycle)
+  std::vector<std::vector<int>> edge_gate_bits;  // per edge: op indices
+  for (size_t i = 0; i < circ->ops.size(); ++i) {
+    const qf_op& o = circ->ops[i];
+    if (o.kind != QF_OP_2Q_DIAG) continue;
+    auto key = std::make_pair(o.q0, o.q1);
+    auto it = p->edge_index.find(key);
+    if (it == p->edge_index.end()) {
+      p->edge_index[key] = (int)edge_gate_bits.size();
+      edge_gate_bits.push_back({});
+      it = p->edge_index.find(key);
+    }
+    edge_gate_bits[it->second].push_back((int)i);
+  }
+  int nl = 0;
+  for (auto& e : edge_gate_bits) {
+    p->edge_label_base.push_back(nl);
+    p->edge_nbits.push_back((int)e.size());
+    nl += (int)e.size();
+  }
+  p->n_bond_labels = nl;
+  const int XBASE = nl;  // label of qubit q's output bit = XBASE + q
+  p->label_cut.assign(nl, -1);
+  p->label_cut_shift.assign(nl, 0);
+
+  // ---- cuts
+  if (d->n_cuts < 0 || (d->n_cuts > 0 && !d->cuts)) return fail(ctx, QF_ERR_PLAN, "bad cut list");
+  int total = 0;
+  for (int c = 0; c < d->n_cuts; ++c) total += d->cuts[c].nbits;
+  if (total > 40) return fail(ctx, QF_ERR_PLAN, "more than 40 cut bits");
+  p->total_cut_bits = total;
+  int off = total;
+  for (int c = 0; c < d->n_cuts; ++c) {
+    qf_cut cut = d->cuts[c];
+    if (cut.q0 > cut.q1) std::swap(cut.q0, cut.q1);
+    auto it = p->edge_index.find({cut.q0, cut.q1});
+    if (it == p->edge_index.end()) return fail(ctx, QF_ERR_PLAN, "cut " + std::to_string(c) + " is not on a bond");
+    const int e = it->second;
+    if (cut.nbits <= 0 || cut.bit_lo < 0 || cut.bit_lo + cut.nbits > p->edge_nbits[e])
+      return fail(ctx, QF_ERR_PLAN, "cut " + std::to_string(c) + ": bit range outside the bond");
+    off -= cut.nbits;
+    p->cut_offset.push_back(off);
+    for (int i = 0; i < cut.nbits; ++i) {
+      const int lab = p->edge_label_base[e] + cut.bit_lo + i;
+      if (p->label_cut[lab] >= 0) return fail(ctx, QF_ERR_PLAN, "bond bit cut twice");
+      p->label_cut[lab] = c;
+      p->label_cut_shift[lab] = off + (cut.nbits - 1 - i);
+    }
+    p->cuts.push_back(cut);
+  }
+
+  // ---- open qubits
+  if (d->n_open < 0 || d->n_open > 30 || (d->n_open > 0 && !d->open)) return fail(ctx, QF_ERR_PLAN, "bad open-qubit list");
+  for (int t = 0; t < d->n_open; ++t) {
+    const int q = d->open[t];
+    if (q < 0 || q >= n || contains(p->open, q)) return fail(ctx, QF_ERR_PLAN, "bad or repeated open qubit");
+    p->open.push_back(q);
+  }
+
+  // ---- world-line programs: T_q[x][bonds in time order], x most significant
+  std::vector<int> nbond(n, 0);
+  for (auto& o : circ->ops)
+    if (o.kind == QF_OP_2Q_DIAG) { ++nbond[o.q0]; ++nbond[o.q1]; }
+  std::vector<std::vector<WlInstr>> progs(n);
+  std::vector<int> seen(n, 0);
+  p->leaf_full_labels.assign(n, {});
+  for (int q = 0; q < n; ++q) p->leaf_full_labels[q].push_back(XBASE + q);
+  std::vector<int> edge_seen(edge_gate_bits.size(), 0);
+  for (size_t i = 0; i < circ->ops.size(); ++i) {
+    const qf_op& o = circ->ops[i];
+    if (o.kind == QF_OP_1Q) {
+      progs[o.q0].push_back({1, (int)i, 0, 0});
+      continue;
+    }
+    const int e = p->edge_index[{o.q0, o.q1}];
+    const int lab = p->edge_label_base[e] + edge_seen[e]++;
+    for (int side = 0; side < 2; ++side) {
+      const int q = side ? o.q1 : o.q0;
+      const int t = seen[q]++;
+      progs[q].push_back({side ? 3 : 2, (int)i, nbond[q] - 1 - t, 0});
+      p->leaf_full_labels[q].push_back(lab);
+    }
+  }
+  p->max_nbond = 0;
+  size_t wl_elems = 0;
+  for (int q = 0; q < n; ++q) {
+    if (nbond[q] > 40) return fail(ctx, QF_ERR_UNSUPPORTED, "world-line with more than 40 bond bits");
+    WlQubit wq;
+    wq.out_offset = (int64_t)wl_elems;
+    wq.first = (int)p->wl_prog.size();
+    wq.count = (int)progs[q].size();
+    wq.nbond = nbond[q];
+    wq.pad = 0;
+    p->wl_prog.insert(p->wl_prog.end(), progs[q].begin(), progs[q].end());
+    p->wl_qubits.push_back(wq);
+    wl_elems += (size_t)2 << nbond[q];
+    p->max_nbond = std::max(p->max_nbond, nbond[q]);
+  }
+
+  // ---- nodes
+  p->nodes.resize(n);
+  for (int q = 0; q < n; ++q) {
+    Node& nd = p->nodes[q];
+    nd.leaf = true;
+    nd.qubit = q;
+    nd.persistent = true;
+    const bool is_open = contains(p->open, q);
+    if (is_open) nd.labels.push_back(XBASE + q);
+    nd.dep_bits = !is_open;
+    for (size_t j = 1; j < p->leaf_full_labels[q].size(); ++j) {
+      const int lab = p->leaf_full_labels[q][j];
+      if (p->label_cut[lab] >= 0) nd.dep_cuts |= (1ull << p->label_cut[lab]);
+      else nd.labels.push_back(lab);
+    }
+  }
+  if (d->n_steps != n - 1 || !d->steps) return fail(ctx, QF_ERR_PLAN, "a plan over n tensors needs exactly n-1 steps");
+  std::vector<char> used(2 * n, 0);
+  p->peak_bits = 0;
+  for (int i = 0; i < d->n_steps; ++i) {
+    const int l = d->steps[2 * i], r = d->steps[2 * i + 1];
+    if (l < 0 || r < 0 || l >= n + i || r >= n + i || l == r)
+      return fail(ctx, QF_ERR_PLAN, "step " + std::to_string(i) + " uses a node that does not exist yet");
+    if (used[l] || used[r]) return fail(ctx, QF_ERR_PLAN, "step " + std::to_string(i) + " reuses a consumed node");
+    used[l] = used[r] = 1;
+    p->nodes[l].consumer = i;
+    p->nodes[r].consumer = i;
+    Node nd;
+    const Node &L = p->nodes[l], &R = p->nodes[r];
+    for (int lab : L.labels) if (!contains(R.labels, lab)) nd.labels.push_back(lab);
+    for (int lab : R.labels) if (!contains(L.labels, lab)) nd.labels.push_back(lab);
+    nd.dep_bits = L.dep_bits || R.dep_bits;
+    nd.dep_cuts = L.dep_cuts | R.dep_cuts;
+    if ((int)nd.labels.size() > 40) return fail(ctx, QF_ERR_UNSUPPORTED, "intermediate tensor above 2^40 elements");
+    p->nodes.push_back(nd);
+    Step st;
+    st.l = l;
+    st.r = r;
+    p->steps.push_back(st);
+    p->peak_bits = std::max({p->peak_bits, (int)nd.labels.size(), (int)L.labels.size(), (int)R.labels.size()});
+  }
+  const Node& root = p->nodes.back();
+  if ((int)root.labels.size() != (int)p->open.size())
+    return fail(ctx, QF_ERR_PLAN, "root tensor keeps bonds: the plan does not contract the whole network");
+  for (int t = 0; t < (int)p->open.size(); ++t) {
+    const int lab = XBASE + p->open[t];
+    const int j = (int)(std::find(root.labels.begin(), root.labels.end(), lab) - root.labels.begin());
+    if (j == (int)root.labels.size()) return fail(ctx, QF_ERR_PLAN, "root misses an open output bit");
+    p->root_pos.push_back((int)root.labels.size() - 1 - j);
+  }
+  // root_pos is needed LSB-first by the accumulate kernel: bit t of j <-> open[k-1-t]
+  std::reverse(p->root_pos.begin(), p->root_pos.end());
+
+  // ---- persistence: a node whose dependencies are a strict subset of its consumer's is reused
+  for (int i = n; i < (int)p->nodes.size() - 1; ++i) {
+    Node& nd = p->nodes[i];
+    const Node& cons = p->nodes[n + nd.consumer];
+    nd.persistent = !(p->flags & QF_PLAN_NO_HOIST) &&
+                    (nd.dep_bits != cons.dep_bits || nd.dep_cuts != cons.dep_cuts);
+  }
+
+  // ---- TTGT roles and layouts
+  p->flops_per_slice = p->flops_hoisted = p->permute_bytes = p->max_step_flops = 0.0;
+  for (int i = 0; i < (int)p->steps.size(); ++i) {
+    Step& st = p->steps[i];
+    Node& out_node = p->nodes[n + i];
+    const Node *X = &p->nodes[st.l], *Y = &p->nodes[st.r];
+    int xid = st.l, yid = st.r;
+    std::vector<int> K;
+    for (int lab : X->labels) if (contains(Y->labels, lab)) K.push_back(lab);
+    int xf = (int)X->labels.size() - (int)K.size(), yf = (int)Y->labels.size() - (int)K.size();
+    if (yf > xf) { std::swap(X, Y); std::swap(xid, yid); std::swap(xf, yf); }
+    // K order: keep an intermediate operand in place when its contracted bits already trail
+    auto trailing = [&](const Node* nd) {
+      if (nd->leaf) return false;
+      const int kb = (int)K.size(), b = (int)nd->labels.size();
+      for (int j = b - kb; j < b; ++j) if (!contains(K, nd->labels[j])) return false;
+      return true;
+    };
+    std::vector<int> korder;
+    if (trailing(X)) korder.assign(X->labels.end() - K.size(), X->labels.end());
+    else if (trailing(Y)) korder.assign(Y->labels.end() - K.size(), Y->labels.end());
+    else korder = K;
+    std::vector<int> xwant, ywant;
+    for (int lab : X->labels) if (!contains(K, lab)) xwant.push_back(lab);
+    for (int lab : Y->labels) if (!contains(K, lab)) ywant.push_back(lab);
+    out_node.labels = xwant;
+    out_node.labels.insert(out_node.labels.end(), ywant.begin(), ywant.end());
+    xwant.insert(xwant.end(), korder.begin(), korder.end());
+    ywant.insert(ywant.end(), korder.begin(), korder.end());
+    auto setup = [&](Operand& op, int id, const Node* nd, const std::vector<int>& want) {
+      op.node = id;
+      op.nbits = (int)want.size();
+      if (nd->leaf) {
+        op.permute = true;
+        op.perm = make_perm(p->leaf_full_labels[nd->qubit], want);
+      } else {
+        op.perm = make_perm(nd->labels, want);
+        op.permute = !is_identity(op.perm);
+      }
+      if (op.permute) p->permute_bytes += 16.0 * std::ldexp(1.0, op.nbits);
+    };
+    setup(st.A, xid, X, xwant);
+    setup(st.B, yid, Y, ywant);
+    st.k_bits = (int)K.size();
+    st.m_bits = xf;
+    st.n_bits = yf;
+    st.flops = 8.0 * std::ldexp(1.0, st.m_bits + st.n_bits + st.k_bits);
+    p->flops_per_slice += st.flops;
+    if (out_node.dep_cuts == 0) p->flops_hoisted += st.flops;
+    p->max_step_flops = std::max(p->max_step_flops, st.flops);
+  }
+
+  // ---- arena
+  size_t cur = kCtxScratch;
+  p->off_gates = cur;
+  cur = align_up(cur + circ->ops.size() * 4 * sizeof(float2));
+  p->off_wlq = cur;
+  cur = align_up(cur + p->wl_qubits.size() * sizeof(WlQubit));
+  p->off_prog = cur;
+  cur = align_up(cur + std::max<size_t>(1, p->wl_prog.size()) * sizeof(WlInstr));
+  p->off_wl = cur;
+  cur = align_up(cur + wl_elems * sizeof(float2));
+  std::vector<Buf> pers, trans;
+  const int S = (int)p->steps.size();
+  for (int i = 0; i < S; ++i) {
+    Node& nd = p->nodes[n + i];
+    const size_t bytes = align_up(sizeof(float2) << nd.labels.size());
+    if (nd.persistent) pers.push_back({bytes, 0, S, &nd.offset});
+    else trans.push_back({bytes, i, (i == S - 1) ? S : nd.consumer, &nd.offset});
+    Step& st = p->steps[i];
+    if (st.A.permute) trans.push_back({align_up(sizeof(float2) << st.A.nbits), i, i, &st.A.buf});
+    if (st.B.permute) trans.push_back({align_up(sizeof(float2) << st.B.nbits), i, i, &st.B.buf});
+  }
+  for (auto& b : pers) { *b.where = cur; cur = align_up(cur + b.bytes); }
+  const size_t tbase = cur;
+  // first fit by address among buffers with overlapping lifetimes, largest first
+  std::vector<int> idx(trans.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return trans[a].bytes > trans[b].bytes; });
+  std::vector<std::pair<size_t, size_t>> placed_rng;  // (offset, end)
+  std::vector<int> placed_id;
+  size_t tend = tbase;
+  for (int id : idx) {
+    const Buf& b = trans[id];
+    std::vector<std::pair<size_t, size_t>> busy;
+    for (size_t j = 0; j < placed_id.size(); ++j) {
+      const Buf& o = trans[placed_id[j]];
+      if (o.start <= b.end && b.start <= o.end) busy.push_back(placed_rng[j]);
+    }
+    std::sort(busy.begin(), busy.end());
+    size_t at = tbase;
+    for (auto& r : busy) {
+      if (at + b.bytes <= r.first) break;
+      at = std::max(at, r.second);
+    }
+    *b.where = at;
+    placed_rng.push_back({at, at + b.bytes});
+    placed_id.push_back(id);
+    tend = std::max(tend, at + b.bytes);
+  }
+  p->arena_end = tend;
+  p->gates_host.resize(circ->ops.size() * 4);
+  *out = p.release();
+  return QF_OK;
+}
+
+void qf_plan_destroy(qf_plan* plan) {
+  if (plan && plan->ctx && plan->ctx->last_built == plan) plan->ctx->last_built = nullptr;
+  delete plan;
+}
+
+// executed flops for one bitstring over slices [s0, s1), with reuse across slices
+static double schedule_flops(const qf_plan* p, int64_t s0, int64_t s1, bool first_bitstring) {
+  double total = 0.0;
+  const int n = p->n;
+  for (int64_t s = s0; s < s1; ++s) {
+    for (size_t i = 0; i < p->steps.size(); ++i) {
+      const Node& nd = p->nodes[n + i];
+      bool run;
+      if (s == s0) run = first_bitstring || nd.dep_bits || (p->flags & QF_PLAN_NO_HOIST);
+      else if (p->flags & QF_PLAN_NO_HOIST) run = true;
+      else {
+        const uint64_t changed = (uint64_t)(s ^ (s - 1));
+        run = false;
+        for (size_t c = 0; c < p->cuts.size(); ++c)
+          if ((nd.dep_cuts >> c) & 1) {
+            const uint64_t mask = ((1ull << p->cuts[c].nbits) - 1) << p->cut_offset[c];
+            if (changed & mask) run = true;
+          }
+      }
+      if (run) total += p->steps[i].flops;
+    }
+  }
+  return total;
+}
+
+qf_status qf_plan_flops(const qf_plan* p, int64_t s_begin, int64_t s_end, double* flops) {
+  if (!p || !flops || s_begin < 0 || s_begin > s_end || s_end > ((int64_t)1 << p->total_cut_bits)) return QF_ERR_ARG;
+  *flops = s_begin == s_end ? 0.0 : schedule_flops(p, s_begin, s_end, true);
+  return QF_OK;
+}
+
+qf_status qf_plan_info_get(const qf_plan* p, qf_plan_info* out) {
+  if (!p || !out) return QF_ERR_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->n_slices = (int64_t)1 << p->total_cut_bits;
+  out->n_open = (int)p->open.size();
+  out->n_steps = (int)p->steps.size();
+  out->peak_bits = p->peak_bits;
+  out->n_qubits = p->n;
+  out->flops_per_slice = p->flops_per_slice;
+  out->flops_hoisted = p->flops_hoisted;
+  out->flops_first_slice = schedule_flops(p, 0, 1, true);
+  const int64_t S = out->n_slices;
+  const int64_t sim = std::min<int64_t>(S, 4096);
+  out->flops_next_slice = sim > 1 ? (schedule_flops(p, 0, sim, true) - out->flops_first_slice) / (double)(sim - 1) : 0.0;
+  out->permute_bytes = p->permute_bytes;
+  out->workspace_bytes = p->arena_end;
+  return QF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+static float2* wsp(qf_ctx* c, size_t off) { return reinterpret_cast<float2*>(c->ws + off); }
+
+static hipEvent_t take_event(qf_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static qf_status build_worldlines(qf_plan* p) {
+  qf_ctx* c = p->ctx;
+  qf_circuit* circ = p->circ;
+  for (size_t i = 0; i < circ->ops.size(); ++i)
+    for (int j = 0; j < 4; ++j) p->gates_host[4 * i + j] = make_float2(circ->ops[i].values[2 * j], circ->ops[i].values[2 * j + 1]);
+  QF_HIP(c, hipMemcpyAsync(c->ws + p->off_gates, p->gates_host.data(), p->gates_host.size() * sizeof(float2),
+                           hipMemcpyHostToDevice, c->stream));
+  QF_HIP(c, hipMemcpyAsync(c->ws + p->off_wlq, p->wl_qubits.data(), p->wl_qubits.size() * sizeof(WlQubit),
+                           hipMemcpyHostToDevice, c->stream));
+  if (!p->wl_prog.empty())
+    QF_HIP(c, hipMemcpyAsync(c->ws + p->off_prog, p->wl_prog.data(), p->wl_prog.size() * sizeof(WlInstr),
+                             hipMemcpyHostToDevice, c->stream));
+  QF_HIP(c, launch_worldlines(c->stream, reinterpret_cast<const WlQubit*>(c->ws + p->off_wlq), p->n, p->max_nbond,
+                              reinterpret_cast<const WlInstr*>(c->ws + p->off_prog),
+                              reinterpret_cast<const float2*>(c->ws + p->off_gates), wsp(c, p->off_wl)));
+  return QF_OK;
+}
+
+static qf_status run_operand(qf_plan* p, const Operand& op, const uint8_t* bits_row, int64_t s, const float2** ptr) {
+  qf_ctx* c = p->ctx;
+  const Node& nd = p->nodes[op.node];
+  if (!op.permute) {
+    *ptr = wsp(c, nd.offset);
+    return QF_OK;
+  }
+  PermuteArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nbits = op.nbits;
+  for (int i = 0; i < op.nbits; ++i) a.perm[i] = op.perm[i];
+  a.scale = 1.0f;
+  const float2* src;
+  if (nd.leaf) {
+    const WlQubit& wq = p->wl_qubits[nd.qubit];
+    src = wsp(c, p->off_wl) + wq.out_offset;
+    int64_t base = 0;
+    const auto& full = p->leaf_full_labels[nd.qubit];
+    const int hb = (int)full.size();
+    for (int j = 1; j < hb; ++j) {
+      const int lab = full[j];
+      if (p->label_cut[lab] >= 0) base += ((s >> p->label_cut_shift[lab]) & 1) << (hb - 1 - j);
+    }
+    a.src_base = base;
+    if (!contains(p->open, nd.qubit)) {
+      a.dyn_bits = bits_row + nd.qubit;
+      a.dyn_stride = (int64_t)1 << wq.nbond;
+    }
+  } else {
+    src = wsp(c, nd.offset);
+  }
+  float2* dst = wsp(c, op.buf);
+  QF_HIP(c, launch_permute(c->stream, src, dst, a));
+  *ptr = dst;
+  return QF_OK;
+}
+
+extern "C" qf_status qf_amplitudes(qf_plan* p, int n_batch, const uint8_t* bits_dev, int64_t s_begin, int64_t s_end,
+                                   double* out_dev) {
+  if (!p) return QF_ERR_ARG;
+  qf_ctx* c = p->ctx;
+  const int64_t S = (int64_t)1 << p->total_cut_bits;
+  if (n_batch < 0 || s_begin < 0 || s_end > S || s_begin > s_end || (n_batch > 0 && (!bits_dev || !out_dev)))
+    return fail(c, QF_ERR_ARG, "qf_amplitudes: bad batch or slice range");
+  if (!c->ws || c->ws_bytes < p->arena_end)
+    return fail(c, QF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p->arena_end) + " bytes");
+  if (n_batch == 0 || s_begin == s_end) return QF_OK;
+  QF_HIP(c, hipSetDevice(c->device));
+  if (c->last_built != p || p->built_version != p->circ->version) {
+    qf_status st = build_worldlines(p);
+    if (st != QF_OK) return st;
+    c->last_built = p;
+    p->built_version = p->circ->version;
+  }
+  int64_t fault_after = -1;
+  if (const char* f = std::getenv("QFMI_FAULT_AFTER_SLICES")) fault_after = std::atoll(f);
+  const int n = p->n;
+  const int k = (int)p->open.size();
+  uint32_t* amax_slots = reinterpret_cast<uint32_t*>(c->ws);  // ctx scratch: 2 slots
+  int64_t done = 0;
+  for (int b = 0; b < n_batch; ++b) {
+    const uint8_t* row = bits_dev + (int64_t)b * n;
+    for (int64_t s = s_begin; s < s_end; ++s) {
+      if (fault_after >= 0 && done >= fault_after)
+        return fail(c, QF_ERR_INJECTED, "fault injected after " + std::to_string(done) + " slices");
+      const uint64_t changed = (s == s_begin) ? ~0ull : (uint64_t)(s ^ (s - 1));
+      for (size_t i = 0; i < p->steps.size(); ++i) {
+        const Step& st = p->steps[i];
+        const Node& nd = p->nodes[n + i];
+        bool run = (s == s_begin) || (p->flags & QF_PLAN_NO_HOIST);
+        if (!run)
+          for (size_t cc = 0; cc < p->cuts.size(); ++cc)
+            if ((nd.dep_cuts >> cc) & 1) {
+              const uint64_t mask = ((1ull << p->cuts[cc].nbits) - 1) << p->cut_offset[cc];
+              if (changed & mask) run = true;
+            }
+        if (!run) continue;
+        const float2 *A, *B;
+        qf_status e1 = run_operand(p, st.A, row, s, &A);
+        if (e1 != QF_OK) return e1;
+        e1 = run_operand(p, st.B, row, s, &B);
+        if (e1 != QF_OK) return e1;
+        float2* C = wsp(c, nd.offset);
+        const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+        const uint32_t *amA = nullptr, *amB = nullptr;
+        if (p->precision == QF_FP16) {
+          QF_HIP(c, launch_amax(c->stream, A, M * K, amax_slots));
+          QF_HIP(c, launch_amax(c->stream, B, N * K, amax_slots + 1));
+          amA = amax_slots;
+          amB = amax_slots + 1;
+        }
+        const bool timed = c->profile && st.flops == p->max_step_flops;
+        hipEvent_t e0 = nullptr, e1v = nullptr;
+        if (timed) {
+          e0 = take_event(c);
+          e1v = take_event(c);
+          if (e0 && e1v) QF_HIP(c, hipEventRecord(e0, c->stream));
+        }
+        QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, 1, 0, 0, 0, amA, amB));
+        if (timed && e0 && e1v) {
+          QF_HIP(c, hipEventRecord(e1v, c->stream));
+          c->ev_used.push_back({e0, e1v});
+          c->prof_flops += st.flops;
+          ++c->prof_launches;
+        }
+      }
+      const Node& root = p->nodes.back();
+      QF_HIP(c, launch_slice_accumulate(c->stream, wsp(c, root.offset), k, p->root_pos.data(),
+                                        reinterpret_cast<double2*>(out_dev) + ((int64_t)b << k)));
+      ++done;
+    }
+  }
+  return QF_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+extern "C" {
+
+qf_status qf_permute(qf_ctx* c, const void* src, void* dst, int nbits, const int32_t* perm, int64_t src_base,
+                     float scale) {
+  if (!c || !src || !dst || nbits < 0 || nbits > 40 || (nbits > 0 && !perm))
+    return fail(c, QF_ERR_ARG, "qf_permute: bad arguments");
+  PermuteArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nbits = nbits;
+  uint64_t seen = 0;
+  for (int i = 0; i < nbits; ++i) {
+    if (perm[i] < 0 || perm[i] > 62 || ((seen >> perm[i]) & 1)) return fail(c, QF_ERR_ARG, "qf_permute: bad permutation");
+    seen |= 1ull << perm[i];
+    a.perm[i] = perm[i];
+  }
+  a.src_base = src_base;
+  a.scale = scale;
+  QF_HIP(c, launch_permute(c->stream, reinterpret_cast<const float2*>(src), reinterpret_cast<float2*>(dst), a));
+  return QF_OK;
+}
+
+qf_status qf_cgemm(qf_ctx* c, int precision, int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C,
+                   int64_t batch, int64_t sa, int64_t sb, int64_t sc) {
+  if (!c || !A || !B || !C || M < 1 || N < 1 || K < 1 || batch < 1 || precision < 0 || precision > 2)
+    return fail(c, QF_ERR_ARG, "qf_cgemm: bad arguments");
+  const uint32_t *amA = nullptr, *amB = nullptr;
+  if (precision == QF_FP16) {
+    if (!c->ws || c->ws_bytes < kCtxScratch) return fail(c, QF_ERR_WORKSPACE, "qf_cgemm FP16 needs a workspace of 4 KiB");
+    if (batch != 1) return fail(c, QF_ERR_UNSUPPORTED, "qf_cgemm FP16 is not batched");
+    uint32_t* slots = reinterpret_cast<uint32_t*>(c->ws);
+    QF_HIP(c, launch_amax(c->stream, reinterpret_cast<const float2*>(A), M * K, slots));
+    QF_HIP(c, launch_amax(c->stream, reinterpret_cast<const float2*>(B), N * K, slots + 1));
+    amA = slots;
+    amB = slots + 1;
+  }
+  QF_HIP(c, launch_cgemm_ex(c->stream, precision, M, N, K, reinterpret_cast<const float2*>(A),
+                            reinterpret_cast<const float2*>(B), reinterpret_cast<float2*>(C), batch, sa, sb, sc, amA, amB));
+  return QF_OK;
+}
+
+qf_status qf_time_cgemm(qf_ctx* c, int precision, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
+                        void* C, int reps, float* ms) {
+  if (!c || !ms || reps < 1) return QF_ERR_ARG;
+  const uint32_t *amA = nullptr, *amB = nullptr;
+  if (precision == QF_FP16) {
+    if (!c->ws || c->ws_bytes < kCtxScratch) return fail(c, QF_ERR_WORKSPACE, "FP16 timing needs a workspace");
+    uint32_t* slots = reinterpret_cast<uint32_t*>(c->ws);
+    QF_HIP(c, launch_amax(c->stream, reinterpret_cast<const float2*>(A), M * K, slots));
+    QF_HIP(c, launch_amax(c->stream, reinterpret_cast<const float2*>(B), N * K, slots + 1));
+    amA = slots;
+    amB = slots + 1;
+  }
+  hipEvent_t e0, e1;
+  QF_HIP(c, hipEventCreate(&e0));
+  QF_HIP(c, hipEventCreate(&e1));
+  QF_HIP(c, launch_cgemm_ex(c->stream, precision, M, N, K, (const float2*)A, (const float2*)B, (float2*)C, 1, 0, 0, 0, amA, amB));
+  QF_HIP(c, hipEventRecord(e0, c->stream));
+  for (int i = 0; i < reps; ++i)
+    QF_HIP(c, launch_cgemm_ex(c->stream, precision, M, N, K, (const float2*)A, (const float2*)B, (float2*)C, 1, 0, 0, 0, amA, amB));
+  QF_HIP(c, hipEventRecord(e1, c->stream));
+  QF_HIP(c, hipEventSynchronize(e1));
+  float t = 0.f;
+  QF_HIP(c, hipEventElapsedTime(&t, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms = t / reps;
+  return QF_OK;
+}
+
+qf_status qf_time_permute(qf_ctx* c, const void* src, void* dst, int nbits, const int32_t* perm, int reps, float* ms) {
+  if (!c || !ms || reps < 1) return QF_ERR_ARG;
+  hipEvent_t e0, e1;
+  QF_HIP(c, hipEventCreate(&e0));
+  QF_HIP(c, hipEventCreate(&e1));
+  qf_status st = qf_permute(c, src, dst, nbits, perm, 0, 1.0f);
+  if (st != QF_OK) return st;
+  QF_HIP(c, hipEventRecord(e0, c->stream));
+  for (int i = 0; i < reps; ++i) {
+    st = qf_permute(c, src, dst, nbits, perm, 0, 1.0f);
+    if (st != QF_OK) return st;
+  }
+  QF_HIP(c, hipEventRecord(e1, c->stream));
+  QF_HIP(c, hipEventSynchronize(e1));
+  float t = 0.f;
+  QF_HIP(c, hipEventElapsedTime(&t, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms = t / reps;
+  return QF_OK;
+}
+
+qf_status qf_profile_enable(qf_ctx* c, int enable) {
+  if (!c) return QF_ERR_ARG;
+  c->profile = enable != 0;
+  return QF_OK;
+}
+
+qf_status qf_profile_read(qf_ctx* c, double* gemm_ms, int64_t* launches, double* flops, int reset) {
+  if (!c) return QF_ERR_ARG;
+  double total = 0.0;
+  for (auto& pr : c->ev_used) {
+    QF_HIP(c, hipEventSynchronize(pr.second));
+    float t = 0.f;
+    QF_HIP(c, hipEventElapsedTime(&t, pr.first, pr.second));
+    total += t;
+  }
+  if (gemm_ms) *gemm_ms = total;
+  if (launches) *launches = c->prof_launches;
+  if (flops) *flops = c->prof_flops;
+  if (reset) {
+    for (auto& pr : c->ev_used) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
+    c->ev_used.clear();
+    c->prof_launches = 0;
+    c->prof_flops = 0.0;
+  }
+  return QF_OK;
+}
+
+}  // extern "C"

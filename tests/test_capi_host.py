@@ -1,0 +1,155 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared symbol, and its
+host logic (circuit and plan validation, shapes, flop counts, slice bookkeeping) is right.
+No compute call is made here: there is no GPU on this side."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1905_00444_amd import _lib
+from workloads.circuits import generate
+from workloads.plans import plan_7x7, sweep_plan, PlanBuilder
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "qfmi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib.EXPORTS, f"binding lacks {name}"
+
+
+def _host_ctx():
+    lib = _lib.load()
+    h = C.c_void_p()
+    assert lib.qf_ctx_create(0, None, None, 0, C.byref(h)) == 0
+    return lib, h
+
+
+def _circuit(lib, ctx, circ):
+    from paper_1905_00444_amd.gates import gate_entries
+    ops = circ.ops
+    arr = (_lib.qf_op * len(ops))()
+    for i, op in enumerate(ops):
+        arr[i].cycle = op.cycle
+        if len(op.qubits) == 1:
+            arr[i].kind, arr[i].q0, arr[i].q1 = 1, op.qubits[0], -1
+        else:
+            arr[i].kind, arr[i].q0, arr[i].q1 = 2, op.qubits[0], op.qubits[1]
+        e = gate_entries(op.name)
+        for j in range(4):
+            arr[i].values[2 * j], arr[i].values[2 * j + 1] = e[j].real, e[j].imag
+    pres = circ.present_mask
+    h = C.c_void_p()
+    st = lib.qf_circuit_create(ctx, circ.rows, circ.cols, pres.ctypes.data_as(C.c_void_p), len(ops), arr, C.byref(h))
+    return st, h
+
+
+def _plan(lib, ctx, ch, plan, precision=0):
+    steps = np.ascontiguousarray(np.asarray(plan["steps"], dtype=np.int32).reshape(-1))
+    cuts = plan.get("cuts", [])
+    carr = (_lib.qf_cut * max(1, len(cuts)))()
+    for i, c in enumerate(cuts):
+        carr[i].q0, carr[i].q1, carr[i].bit_lo, carr[i].nbits = c
+    opn = np.ascontiguousarray(np.asarray(plan.get("open", []), dtype=np.int32))
+    d = _lib.qf_plan_desc()
+    d.n_steps = len(steps) // 2
+    d.steps = steps.ctypes.data_as(C.POINTER(C.c_int32))
+    d.n_cuts = len(cuts)
+    d.cuts = carr
+    d.n_open = len(opn)
+    d.open = opn.ctypes.data_as(C.POINTER(C.c_int32)) if len(opn) else None
+    d.precision = precision
+    h = C.c_void_p()
+    st = lib.qf_plan_create(ctx, ch, C.byref(d), C.byref(h))
+    return st, h
+
+
+def test_plan_info_matches_paper_flop_formula_7x7_d40():
+    lib, ctx = _host_ctx()
+    c = generate(7, 7, 40, 0)
+    plan, pb = plan_7x7(c, 40)
+    st, ch = _circuit(lib, ctx, c)
+    assert st == 0
+    st, ph = _plan(lib, ctx, ch, plan)
+    assert st == 0, lib.qf_last_error(ctx)
+    inf = _lib.qf_plan_info()
+    assert lib.qf_plan_info_get(ph, C.byref(inf)) == 0
+    assert inf.n_slices == 1024 and inf.n_open == 6 and inf.peak_bits == 30
+    # F = 8 sqrt(v0 v1 v2) summed over steps, sizes from the plan builder
+    want = 0.0
+    for (a, b), vc in zip(plan["steps"], pb.sizes()):
+        va, vb = pb.bits_of(pb.members[a]), pb.bits_of(pb.members[b])
+        want += 8 * 2.0 ** ((va + vb + vc) / 2)
+    assert abs(inf.flops_per_slice - want) / want < 1e-12
+    # the A x B subtree does not depend on the second cut: later slices reuse it
+    assert inf.flops_next_slice < inf.flops_first_slice
+    f6 = C.c_double()
+    assert lib.qf_plan_flops(ph, 0, 6, C.byref(f6)) == 0
+    assert f6.value < 6 * inf.flops_per_slice
+    assert inf.workspace_bytes > 4 * 8 * 2 ** 30  # several 2^30 complex64 tensors live at once
+    lib.qf_plan_destroy(ph)
+    lib.qf_circuit_destroy(ch)
+    lib.qf_ctx_destroy(ctx)
+
+
+def test_plan_validation_errors():
+    lib, ctx = _host_ctx()
+    c = generate(3, 3, 8, 0)
+    st, ch = _circuit(lib, ctx, c)
+    good = sweep_plan(c)
+    st, ph = _plan(lib, ctx, ch, good)
+    assert st == 0
+    lib.qf_plan_destroy(ph)
+    bad = {"steps": [[0, 1], [0, 2]] + good["steps"][2:], "cuts": [], "open": []}
+    assert _plan(lib, ctx, ch, bad)[0] == _lib.QF_ERR_PLAN
+    bad = {"steps": good["steps"][:-1], "cuts": [], "open": []}
+    assert _plan(lib, ctx, ch, bad)[0] == _lib.QF_ERR_PLAN
+    bad = dict(good, cuts=[[0, 4, 0, 1]])  # (0,0)-(1,1) is not a bond
+    assert _plan(lib, ctx, ch, bad)[0] == _lib.QF_ERR_PLAN
+    bad = dict(good, cuts=[[0, 1, 0, 2]])  # bond (0,1) has one bit at depth 8
+    assert _plan(lib, ctx, ch, bad)[0] == _lib.QF_ERR_PLAN
+    bad = dict(good, open=[3, 3])
+    assert _plan(lib, ctx, ch, bad)[0] == _lib.QF_ERR_PLAN
+    assert "open" in lib.qf_last_error(ctx).decode()
+    lib.qf_circuit_destroy(ch)
+    lib.qf_ctx_destroy(ctx)
+
+
+def test_circuit_validation_errors():
+    lib, ctx = _host_ctx()
+    c = generate(3, 3, 8, 0)
+    from workloads.circuits import Circuit, Op
+    bad = Circuit(3, 3, (), list(c.ops) + [Op(9, "cz", (0, 4))])  # diagonal neighbours
+    st, _ = _circuit(lib, ctx, bad)
+    assert st == _lib.QF_ERR_ARG
+    bad = Circuit(3, 3, (), list(c.ops) + [Op(9, "t", (9,))])
+    st, _ = _circuit(lib, ctx, bad)
+    assert st == _lib.QF_ERR_ARG
+    lib.qf_ctx_destroy(ctx)
+
+
+def test_workspace_required_before_compute():
+    lib, ctx = _host_ctx()
+    c = generate(3, 3, 8, 0)
+    st, ch = _circuit(lib, ctx, c)
+    st, ph = _plan(lib, ctx, ch, sweep_plan(c))
+    out = C.c_void_p(16)
+    bits = C.c_void_p(16)
+    # no workspace: the call must refuse before touching the device
+    assert lib.qf_amplitudes(ph, 1, bits, 0, 1, out) == _lib.QF_ERR_WORKSPACE
+    assert lib.qf_amplitudes(ph, 1, bits, 0, 2, out) == _lib.QF_ERR_ARG  # 1 slice only
+    lib.qf_plan_destroy(ph)
+    lib.qf_circuit_destroy(ch)
+    lib.qf_ctx_destroy(ctx)

@@ -1,0 +1,196 @@
+"""End-to-end parity of the HIP path (through the C-ABI) with the FP64 oracle and with
+closed forms, at the benchmark configurations' shapes."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import sv, tn
+from oracle.metrics import rel_err
+from workloads.bitstrings import random_bitstrings, all_bitstrings
+from workloads.circuits import generate, identity_cz, mirror
+from workloads.plans import sweep_plan, region_plan, plan_7x7
+
+pytestmark = pytest.mark.gpu
+
+# norm-wise relative error bounds against FP64 (FP32 and split-BF16 targets; FP16 stated)
+BOUND = {"fp32": 1e-5, "bf16x3": 1e-4, "fp16": 3e-2}
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1905_00444_amd import Context
+    assert torch.cuda.is_available()
+    return Context(0)
+
+
+def _amps(ctx, circ, plan, bits, precision="fp32", s_begin=0, s_end=None, hoist=True):
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    c = Circuit(ctx, circ.to_text())
+    p = Plan(ctx, c, plan, precision, hoist=hoist)
+    out = p.amplitudes(bits, s_begin, s_end)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16"])
+def test_4x4_d16_64_bitstrings_vs_state_vector(ctx, precision):
+    _say(f"4x4 d16 64 bitstrings {precision}")
+    c = generate(4, 4, 16, 0)
+    bits = random_bitstrings(64, 16, 1)
+    got = _amps(ctx, c, sweep_plan(c), bits, precision)[:, 0]
+    ref = sv.amplitudes(c.to_text(), bits)
+    assert rel_err(got, ref) <= BOUND[precision]
+
+
+def test_4x4_d16_all_amplitudes_unit_norm(ctx):
+    _say("4x4 d16 all 2^16 amplitudes")
+    c = generate(4, 4, 16, 0)
+    open_q = list(range(8, 16))
+    prefixes = np.zeros((256, 16), dtype=np.uint8)
+    prefixes[:, :8] = all_bitstrings(8)
+    got = _amps(ctx, c, sweep_plan(c, open_qubits=open_q), prefixes)
+    psi = sv.final_state(c.to_text())
+    assert rel_err(got.reshape(-1), psi) <= 1e-5
+    assert abs(np.sum(np.abs(got) ** 2) - 1.0) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16"])
+def test_4x5_d32_regions_cuts_open_vs_state_vector(ctx, precision):
+    _say(f"4x5 d32 regions {precision}")
+    c = generate(4, 5, 32, 2)
+    qid = c.qubit_of()
+    cuts = [[qid[(1, 3)], qid[(2, 3)], 0, 2], [qid[(3, 1)], qid[(3, 2)], 1, 2]]
+    plan, _ = region_plan(c, 2, 2, cuts, [(3, 4), (2, 4), (3, 3)])
+    bits = random_bitstrings(4, 20, 3)
+    got = _amps(ctx, c, plan, bits, precision)
+    ref = sv.open_amplitudes(c.to_text(), bits, plan["open"])
+    assert rel_err(got, ref) <= BOUND[precision]
+
+
+def test_6x6_d24_vs_tensor_network_oracle(ctx):
+    _say("6x6 d24 vs oracle-TN")
+    c = generate(6, 6, 24, 0)
+    bits = random_bitstrings(3, 36, 1)
+    plan = sweep_plan(c)
+    got = _amps(ctx, c, plan, bits, "fp32")[:, 0]
+    ref = tn.amplitudes(c.to_text(), bits, plan)[:, 0]
+    assert rel_err(got, ref) <= 1e-5
+    got16 = _amps(ctx, c, plan, bits, "bf16x3")[:, 0]
+    assert rel_err(got16, ref) <= 1e-4
+
+
+def test_hoisting_and_slice_ranges_are_exact(ctx):
+    """Reusing slice-independent subtrees, and splitting the slice range, change nothing."""
+    _say("hoist / slice range")
+    c = generate(4, 5, 32, 2)
+    qid = c.qubit_of()
+    cuts = [[qid[(1, 3)], qid[(2, 3)], 0, 2], [qid[(3, 1)], qid[(3, 2)], 1, 2]]
+    plan, _ = region_plan(c, 2, 2, cuts, [(3, 4)])
+    bits = random_bitstrings(2, 20, 4)
+    a = _amps(ctx, c, plan, bits, "fp32")
+    b = _amps(ctx, c, plan, bits, "fp32", hoist=False)
+    assert np.array_equal(a, b)
+    part = _amps(ctx, c, plan, bits, "fp32", 0, 5)
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    cc = Circuit(ctx, c.to_text())
+    p = Plan(ctx, cc, plan, "fp32")
+    out = p.amplitudes(bits, 0, 5)
+    p.amplitudes(bits, 5, 16, out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), a)
+    assert not np.allclose(part, a)
+
+
+def test_fault_injection_and_resume(ctx, monkeypatch):
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan, _lib
+    _say("fault injection")
+    c = generate(4, 5, 32, 2)
+    qid = c.qubit_of()
+    plan, _ = region_plan(c, 2, 2, [[qid[(1, 3)], qid[(2, 3)], 0, 3]], [(3, 4)])
+    bits = random_bitstrings(1, 20, 4)
+    full = _amps(ctx, c, plan, bits, "fp32")
+    cc = Circuit(ctx, c.to_text())
+    p = Plan(ctx, cc, plan, "fp32")
+    monkeypatch.setenv("QFMI_FAULT_AFTER_SLICES", "3")
+    with pytest.raises(_lib.QfError) as e:
+        out = torch.zeros((1, 2), dtype=torch.complex128, device="cuda")
+        p.amplitudes(bits, 0, 8, out=out)
+    assert e.value.status == _lib.QF_ERR_INJECTED
+    monkeypatch.delenv("QFMI_FAULT_AFTER_SLICES")
+    p.amplitudes(bits, 3, 8, out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), full)
+
+
+def _product_slice_closed_form(circ, plan, bits_row, s):
+    """Closed form of one slice when every CZ is the identity: the network factorises per
+    qubit; a cut bond bit k fixes the q0-side projector |k><k| at that gate's time."""
+    from oracle import gates
+    cuts = plan["cuts"]
+    total = sum(c[3] for c in cuts)
+    fixed = {}
+    off = total
+    for q0, q1, lo, nb in cuts:
+        off -= nb
+        v = (s >> off) & ((1 << nb) - 1)
+        for i in range(nb):
+            fixed[(q0, q1, lo + i)] = (v >> (nb - 1 - i)) & 1
+    n = circ.n_qubits
+    vecs = [np.array([1, 0], dtype=np.complex128) for _ in range(n)]
+    seen = {}
+    for op in circ.ops:
+        if len(op.qubits) == 1:
+            q = op.qubits[0]
+            vecs[q] = gates.one_qubit(op.name) @ vecs[q]
+        else:
+            q0, q1 = op.qubits
+            j = seen.get((q0, q1), 0)
+            seen[(q0, q1)] = j + 1
+            if (q0, q1, j) in fixed:
+                k = fixed[(q0, q1, j)]
+                vecs[q0] = vecs[q0] * (np.arange(2) == k)
+    opn = plan["open"]
+    closed = [vecs[q][bits_row[q]] for q in range(n) if q not in opn]
+    amp = np.prod(closed)
+    out = np.array([amp], dtype=np.complex128)
+    for q in opn:
+        out = np.outer(out, vecs[q]).reshape(-1)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_product_circuit_full_7x7_d40_shape_one_slice(ctx, precision):
+    """Every tensor of the 7x7 (1+40+1) workload at full size (peak 2^30), CZ -> identity."""
+    _say(f"7x7 d40 product circuit, slice 37, {precision}")
+    base = generate(7, 7, 40, 0)
+    plan, _ = plan_7x7(base, 40)
+    c = identity_cz(base)
+    bits = random_bitstrings(1, 49, 1)
+    s = 37
+    got = _amps(ctx, c, plan, bits, precision, s, s + 1)[0]
+    ref = _product_slice_closed_form(c, plan, bits[0], s)
+    assert rel_err(got, ref) <= BOUND[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_mirror_circuit_7x7_bond16_all_slices(ctx, precision):
+    """V^dagger V on 7x7 with 16+16 cycles has bond dimension 16 (the 7x7 (1+32+1) shape):
+    a(0...0) = 1 and every other amplitude 0, summed over all 16 slices."""
+    _say(f"7x7 mirror, 16 slices, {precision}")
+    base = generate(7, 7, 32, 0)
+    plan, _ = plan_7x7(base, 32)
+    m = mirror(base, 16, 5)
+    bits = np.zeros((1, 49), dtype=np.uint8)
+    got = _amps(ctx, m, plan, bits, precision)[0]
+    want = np.zeros(64, dtype=np.complex128)
+    want[0] = 1.0
+    assert np.max(np.abs(got - want)) <= (2e-5 if precision == "fp32" else 2e-4)
