@@ -72,8 +72,10 @@ typedef struct {
 } qf_cut;
 
 enum {
-  QF_PLAN_NO_HOIST = 1 /* recompute every step for every slice (no reuse of slice-independent
-                          subtrees across slices) */
+  QF_PLAN_NO_HOIST = 1, /* recompute every step for every slice (no reuse of slice-independent
+                           subtrees across slices) */
+  QF_PLAN_BACKWARD = 2  /* keep every forward tensor and reserve environment buffers so that
+                           qf_backward can run (implies QF_PLAN_NO_HOIST; larger workspace) */
 };
 
 /* Contraction plan.  steps: 2*n_steps node ids (lhs, rhs) in execution order.  Ids 0..n-1
@@ -143,6 +145,20 @@ void qf_plan_destroy(qf_plan* plan);
  * Errors: QF_ERR_ARG (range), QF_ERR_WORKSPACE, QF_ERR_HIP, QF_ERR_INJECTED. */
 qf_status qf_amplitudes(qf_plan* plan, int n_batch, const uint8_t* bits_dev, int64_t s_begin,
                         int64_t s_end, double* out_dev);
+
+/* Gradients of the amplitudes with respect to every gate entry (reverse sweep over the same
+ * contraction tree with the same kernels, then through each world-line).  Needs a plan created
+ * with QF_PLAN_BACKWARD.  For every slice in [s_begin, s_end) the forward pass is recomputed
+ * and its environment tensors are propagated back.
+ *   cot_dev : device, n_batch x 2^n_open complex128 cotangents c_b of the amplitudes a_b
+ *             (for L = sum |a_b|^2, c_b = 2 a_b).
+ *   grad_dev: device, n_ops x 4 complex64 in the caller's gate order (2x2 row-major matrix, or
+ *             the 4 diagonal entries), ACCUMULATED (+=):
+ *             grad_G += sum_b c_b * conj(d a_b / d G)   (= dL/dRe G + i dL/dIm G).
+ * Errors: QF_ERR_ARG, QF_ERR_UNSUPPORTED (plan not created for backward), QF_ERR_WORKSPACE,
+ * QF_ERR_HIP. */
+qf_status qf_backward(qf_plan* plan, int n_batch, const uint8_t* bits_dev, const double* cot_dev,
+                      int64_t s_begin, int64_t s_end, float* grad_dev);
 
 /* --- kernel-level entry points (the steps of one contraction; used by tests and bench) --- */
 

@@ -14,6 +14,7 @@ QF_OK, QF_ERR_ARG, QF_ERR_PLAN, QF_ERR_WORKSPACE, QF_ERR_HIP, QF_ERR_UNSUPPORTED
 QF_FP32, QF_BF16X3, QF_FP16 = 0, 1, 2
 QF_OP_1Q, QF_OP_2Q_DIAG = 1, 2
 QF_PLAN_NO_HOIST = 1
+QF_PLAN_BACKWARD = 2
 
 STATUS_NAMES = {0: "QF_OK", -1: "QF_ERR_ARG", -2: "QF_ERR_PLAN", -3: "QF_ERR_WORKSPACE", -4: "QF_ERR_HIP",
                 -5: "QF_ERR_UNSUPPORTED", -6: "QF_ERR_INJECTED"}
@@ -56,6 +57,7 @@ EXPORTS = {
     "qf_plan_destroy": (None, [C.c_void_p]),
     "qf_plan_flops": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
     "qf_amplitudes": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]),
+    "qf_backward": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]),
     "qf_permute": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_int64,
                              C.c_float]),
     "qf_cgemm": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,

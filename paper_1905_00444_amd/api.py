@@ -133,7 +133,8 @@ class Circuit:
 
 
 class Plan:
-    def __init__(self, ctx: Context, circuit: Circuit, plan: dict, precision: str = "fp32", hoist: bool = True):
+    def __init__(self, ctx: Context, circuit: Circuit, plan: dict, precision: str = "fp32", hoist: bool = True,
+                 backward: bool = False):
         self.ctx = ctx
         self.circuit = circuit
         self.plan = plan
@@ -153,7 +154,7 @@ class Plan:
         d.n_open = len(opn)
         d.open = opn.ctypes.data_as(C.POINTER(C.c_int32)) if len(opn) else None
         d.precision = PRECISIONS[precision]
-        d.flags = 0 if hoist else _lib.QF_PLAN_NO_HOIST
+        d.flags = (0 if hoist else _lib.QF_PLAN_NO_HOIST) | (_lib.QF_PLAN_BACKWARD if backward else 0)
         h = C.c_void_p()
         check(ctx.lib.qf_plan_create(ctx.h, circuit.h, C.byref(d), C.byref(h)), ctx.h)
         self.h = h
@@ -191,6 +192,30 @@ class Plan:
         self._bits_keepalive = bits_t
         check(st, self.ctx.h)
         return out
+
+    def backward(self, bits, cot, s_begin: int = 0, s_end: Optional[int] = None, grad=None):
+        """Gradient (n_ops, 4) complex64 of the amplitudes contracted with the cotangent `cot`
+        (n_batch, 2^n_open complex128): grad_G = sum_b cot_b conj(d a_b / d G), added into `grad`."""
+        torch = _torch()
+        info = self.info()
+        if s_end is None:
+            s_end = info["n_slices"]
+        self.ctx.ensure_workspace(info["workspace_bytes"])
+        if isinstance(bits, np.ndarray):
+            bits_t = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint8)).to(self.ctx.device)
+        else:
+            bits_t = bits.to(device=self.ctx.device, dtype=torch.uint8).contiguous()
+        cot_t = torch.as_tensor(cot).to(device=self.ctx.device, dtype=torch.complex128).contiguous()
+        assert cot_t.shape == (bits_t.shape[0], 2 ** self.n_open)
+        if grad is None:
+            grad = torch.zeros((len(self.circuit.ops), 4), dtype=torch.complex64, device=self.ctx.device)
+        with torch.cuda.stream(self.ctx.stream):
+            st = self.ctx.lib.qf_backward(self.h, bits_t.shape[0], C.c_void_p(bits_t.data_ptr()),
+                                          C.c_void_p(cot_t.data_ptr()), int(s_begin), int(s_end),
+                                          C.c_void_p(grad.data_ptr()))
+        self._bwd_keepalive = (bits_t, cot_t)
+        check(st, self.ctx.h)
+        return grad
 
     def __del__(self):
         try:

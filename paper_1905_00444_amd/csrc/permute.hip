@@ -34,6 +34,7 @@ struct PermKernelArgs {
   float scale;
   const uint8_t* dyn_bits;
   int64_t dyn_stride;
+  float conj_sign;          // -1 to conjugate
 };
 
 __device__ __forceinline__ int lds_index(int u) { return u + (u >> 5); }
@@ -70,7 +71,7 @@ permute_kernel(const float2* __restrict__ src, float2* __restrict__ dst, PermKer
       }
     float2 x = tile[lds_index(u)];
     x.x *= a.scale;
-    x.y *= a.scale;
+    x.y *= a.scale * a.conj_sign;
     dst[dbase + off] = x;
   }
 }
@@ -108,11 +109,48 @@ hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const 
   a.scale = p.scale;
   a.dyn_bits = p.dyn_bits;
   a.dyn_stride = p.dyn_stride;
+  a.conj_sign = p.conj ? -1.f : 1.f;
   const int64_t tiles = (int64_t)1 << no;
   const unsigned gx = (unsigned)std::min<int64_t>(tiles, 65536);
   const unsigned gy = (unsigned)(tiles / gx);
   const size_t lds = (size_t)((1 << t) + (1 << t) / 32 + 1) * sizeof(float2);
   hipLaunchKernelGGL(permute_kernel, dim3(gx, gy), dim3(kPermThreads), lds, st, src, dst, a);
+  return hipGetLastError();
+}
+
+// Adjoint of the gather (used by the backward pass on world-line slices, at most a few million
+// elements): one thread per source element, distinct destinations within one launch.
+struct ScatterArgs {
+  int nbits;
+  int perm[64];
+  int64_t base;
+};
+
+__global__ void __launch_bounds__(256)
+scatter_add_kernel(const float2* __restrict__ src, float2* __restrict__ dst, ScatterArgs a,
+                   const uint8_t* dyn_bits, int64_t dyn_stride) {
+  const int64_t n = (int64_t)1 << a.nbits;
+  int64_t base = a.base;
+  if (dyn_bits) base += (int64_t)(dyn_bits[0] & 1) * dyn_stride;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    int64_t off = base;
+    for (int i = 0; i < a.nbits; ++i) off |= ((j >> i) & 1) << a.perm[i];
+    const float2 v = src[j];
+    float2 d = dst[off];
+    d.x += v.x;
+    d.y += v.y;
+    dst[off] = d;
+  }
+}
+
+hipError_t launch_scatter_add(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& p) {
+  ScatterArgs a = {};
+  a.nbits = p.nbits;
+  for (int i = 0; i < p.nbits; ++i) a.perm[i] = p.perm[i];
+  a.base = p.src_base;
+  const int64_t n = (int64_t)1 << p.nbits;
+  unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(scatter_add_kernel, dim3(blocks), dim3(256), 0, st, src, dst, a, p.dyn_bits, p.dyn_stride);
   return hipGetLastError();
 }
 

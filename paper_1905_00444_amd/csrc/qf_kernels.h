@@ -11,7 +11,7 @@ struct WlInstr {
                   // 3: bond from the q1 side (diagonal entries)
   int32_t gate;   // index into the gate-value table
   int32_t bitpos; // bit position of the created bond in the world-line index (kinds 2, 3)
-  int32_t pad;
+  int32_t out;    // index of the gate in the caller's order (gradient output row)
 };
 
 struct WlQubit {
@@ -35,15 +35,29 @@ struct PermuteArgs {
   float scale;
   const uint8_t* dyn_bits;
   int64_t dyn_stride;
+  int conj;  // conjugate while copying
 };
 hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& a);
+
+// Adjoint of the gather: dst[src_base + sum_i bit_i(j) << perm[i]] += src[j] (same args).
+hipError_t launch_scatter_add(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& a);
+
+// Gradients of every gate from the world-line environments env (same layout as the
+// world-lines): grad[out][e] += sum over tensor elements (complex64, 4 entries per gate).
+hipError_t launch_worldline_grad(hipStream_t st, const WlQubit* qubits, int n_qubits, int max_nbond,
+                                 const WlInstr* prog, const float2* gates, const float2* env, float2* grad);
+
+// env_root[sum_t bit_t(j) << pos[t]] = cot[j] (complex128 -> complex64), j < 2^k.
+hipError_t launch_seed_root(hipStream_t st, const double2* cot, int k, const int* pos, float2* env_root);
+
+hipError_t launch_zero(hipStream_t st, void* p, size_t bytes);
 
 // Batched complex GEMM, C[m][n] = sum_k A[m][k] B[n][k].
 hipError_t launch_cgemm(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K,
                         const float2* A, const float2* B, float2* C, int64_t batch, int64_t sa,
                         int64_t sb, int64_t sc);
 
-// out[j] += 2^scale_exp * root[sum_t bit_t(j) * 2^pos[t]] in complex128, j < 2^k.
+// out[j] += root[sum_t bit_t(j) << pos[t]] in complex128, j < 2^k.
 hipError_t launch_slice_accumulate(hipStream_t st, const float2* root, int k, const int* pos,
                                    double2* out);
 

@@ -75,6 +75,7 @@ struct Node {
   uint64_t dep_cuts = 0;    // bit c: depends on cut c's value
   bool persistent = false;
   size_t offset = 0;        // arena byte offset of the dense result (intermediates)
+  size_t env = 0;           // arena byte offset of its environment (backward plans)
   int consumer = -1;        // step index that uses it
 };
 
@@ -132,6 +133,10 @@ struct qf_plan {
   double max_step_flops = 0.0;
   // arena (offsets relative to the workspace start)
   size_t off_gates = 0, off_wlq = 0, off_prog = 0, off_wl = 0, arena_end = 0;
+  // backward plans: world-line environments and per-step scratch
+  bool backward = false;
+  size_t wl_elems = 0;
+  size_t off_envwl = 0, off_bq = 0, off_bp = 0, off_bea = 0, off_beb = 0;
   std::vector<float2> gates_host;
   int64_t built_version = -1;
 };
@@ -275,6 +280,8 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   p->n = n;
   p->precision = d->precision;
   p->flags = d->flags;
+  p->backward = (d->flags & QF_PLAN_BACKWARD) != 0;
+  if (p->backward) p->flags |= QF_PLAN_NO_HOIST;
 
   // ---- bonds: one bit per diagonal two-qubit gate, time order (ops are sorted by cycle)
   std::vector<std::vector<int>> edge_gate_bits;  // per edge: op indices
@@ -347,7 +354,7 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   for (size_t i = 0; i < circ->ops.size(); ++i) {
     const qf_op& o = circ->ops[i];
     if (o.kind == QF_OP_1Q) {
-      progs[o.q0].push_back({1, (int)i, 0, 0});
+      progs[o.q0].push_back({1, (int)i, 0, circ->order[i]});
       continue;
     }
     const int e = p->edge_index[{o.q0, o.q1}];
@@ -355,7 +362,7 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     for (int side = 0; side < 2; ++side) {
       const int q = side ? o.q1 : o.q0;
       const int t = seen[q]++;
-      progs[q].push_back({side ? 3 : 2, (int)i, nbond[q] - 1 - t, 0});
+      progs[q].push_back({side ? 3 : 2, (int)i, nbond[q] - 1 - t, circ->order[i]});
       p->leaf_full_labels[q].push_back(lab);
     }
   }
@@ -373,7 +380,10 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     p->wl_qubits.push_back(wq);
     wl_elems += (size_t)2 << nbond[q];
     p->max_nbond = std::max(p->max_nbond, nbond[q]);
+    if (p->backward && wq.count > 160)
+      return fail(ctx, QF_ERR_UNSUPPORTED, "backward plans support at most 160 gates per qubit");
   }
+  p->wl_elems = wl_elems;
 
   // ---- nodes
   p->nodes.resize(n);
@@ -503,11 +513,35 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   for (int i = 0; i < S; ++i) {
     Node& nd = p->nodes[n + i];
     const size_t bytes = align_up(sizeof(float2) << nd.labels.size());
+    Step& st = p->steps[i];
+    if (p->backward) {
+      // every forward tensor is kept for the reverse sweep, next to its environment
+      pers.push_back({bytes, 0, S, &nd.offset});
+      pers.push_back({bytes, 0, S, &nd.env});
+      if (st.A.permute) pers.push_back({align_up(sizeof(float2) << st.A.nbits), 0, S, &st.A.buf});
+      if (st.B.permute) pers.push_back({align_up(sizeof(float2) << st.B.nbits), 0, S, &st.B.buf});
+      continue;
+    }
     if (nd.persistent) pers.push_back({bytes, 0, S, &nd.offset});
     else trans.push_back({bytes, i, (i == S - 1) ? S : nd.consumer, &nd.offset});
-    Step& st = p->steps[i];
     if (st.A.permute) trans.push_back({align_up(sizeof(float2) << st.A.nbits), i, i, &st.A.buf});
     if (st.B.permute) trans.push_back({align_up(sizeof(float2) << st.B.nbits), i, i, &st.B.buf});
+  }
+  if (p->backward) {
+    size_t max_q = 0, max_c = 0, max_a = 0, max_b = 0;
+    for (int i = 0; i < S; ++i) {
+      const Step& st = p->steps[i];
+      const size_t va = sizeof(float2) << st.A.nbits, vb = sizeof(float2) << st.B.nbits;
+      max_q = std::max({max_q, va, vb});
+      max_c = std::max(max_c, sizeof(float2) << (st.m_bits + st.n_bits));
+      max_a = std::max(max_a, va);
+      max_b = std::max(max_b, vb);
+    }
+    pers.push_back({align_up(wl_elems * sizeof(float2)), 0, S, &p->off_envwl});
+    pers.push_back({align_up(max_q), 0, S, &p->off_bq});
+    pers.push_back({align_up(max_c), 0, S, &p->off_bp});
+    pers.push_back({align_up(max_a), 0, S, &p->off_bea});
+    pers.push_back({align_up(max_b), 0, S, &p->off_beb});
   }
   for (auto& b : pers) { *b.where = cur; cur = align_up(cur + b.bytes); }
   const size_t tbase = cur;
@@ -631,6 +665,29 @@ static qf_status build_worldlines(qf_plan* p) {
   return QF_OK;
 }
 
+// Leaf gather arguments: the fixed bits of a world-line (cut bits of slice s, the output bit
+// read from the bitstring on the device) go into the base; the free bits follow op.perm.
+static void leaf_args(const qf_plan* p, const Node& nd, const Operand& op, const uint8_t* bits_row, int64_t s,
+                      PermuteArgs* a) {
+  std::memset(a, 0, sizeof(*a));
+  a->nbits = op.nbits;
+  for (int i = 0; i < op.nbits; ++i) a->perm[i] = op.perm[i];
+  a->scale = 1.0f;
+  const WlQubit& wq = p->wl_qubits[nd.qubit];
+  int64_t base = 0;
+  const auto& full = p->leaf_full_labels[nd.qubit];
+  const int hb = (int)full.size();
+  for (int j = 1; j < hb; ++j) {
+    const int lab = full[j];
+    if (p->label_cut[lab] >= 0) base += ((s >> p->label_cut_shift[lab]) & 1) << (hb - 1 - j);
+  }
+  a->src_base = base;
+  if (!contains(p->open, nd.qubit)) {
+    a->dyn_bits = bits_row + nd.qubit;
+    a->dyn_stride = (int64_t)1 << wq.nbond;
+  }
+}
+
 static qf_status run_operand(qf_plan* p, const Operand& op, const uint8_t* bits_row, int64_t s, const float2** ptr) {
   qf_ctx* c = p->ctx;
   const Node& nd = p->nodes[op.node];
@@ -639,32 +696,78 @@ static qf_status run_operand(qf_plan* p, const Operand& op, const uint8_t* bits_
     return QF_OK;
   }
   PermuteArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.nbits = op.nbits;
-  for (int i = 0; i < op.nbits; ++i) a.perm[i] = op.perm[i];
-  a.scale = 1.0f;
   const float2* src;
   if (nd.leaf) {
-    const WlQubit& wq = p->wl_qubits[nd.qubit];
-    src = wsp(c, p->off_wl) + wq.out_offset;
-    int64_t base = 0;
-    const auto& full = p->leaf_full_labels[nd.qubit];
-    const int hb = (int)full.size();
-    for (int j = 1; j < hb; ++j) {
-      const int lab = full[j];
-      if (p->label_cut[lab] >= 0) base += ((s >> p->label_cut_shift[lab]) & 1) << (hb - 1 - j);
-    }
-    a.src_base = base;
-    if (!contains(p->open, nd.qubit)) {
-      a.dyn_bits = bits_row + nd.qubit;
-      a.dyn_stride = (int64_t)1 << wq.nbond;
-    }
+    leaf_args(p, nd, op, bits_row, s, &a);
+    src = wsp(c, p->off_wl) + p->wl_qubits[nd.qubit].out_offset;
   } else {
+    std::memset(&a, 0, sizeof(a));
+    a.nbits = op.nbits;
+    for (int i = 0; i < op.nbits; ++i) a.perm[i] = op.perm[i];
+    a.scale = 1.0f;
     src = wsp(c, nd.offset);
   }
   float2* dst = wsp(c, op.buf);
   QF_HIP(c, launch_permute(c->stream, src, dst, a));
   *ptr = dst;
+  return QF_OK;
+}
+
+// One GEMM of the plan's precision (FP16 takes the operands' max magnitudes first).
+static qf_status plan_gemm(qf_plan* p, int64_t M, int64_t N, int64_t K, const float2* A, const float2* B, float2* C) {
+  qf_ctx* c = p->ctx;
+  const uint32_t *amA = nullptr, *amB = nullptr;
+  if (p->precision == QF_FP16) {
+    uint32_t* slots = reinterpret_cast<uint32_t*>(c->ws);  // context scratch: 2 slots
+    QF_HIP(c, launch_amax(c->stream, A, M * K, slots));
+    QF_HIP(c, launch_amax(c->stream, B, N * K, slots + 1));
+    amA = slots;
+    amB = slots + 1;
+  }
+  QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, 1, 0, 0, 0, amA, amB));
+  return QF_OK;
+}
+
+static qf_status run_step(qf_plan* p, size_t i, const uint8_t* row, int64_t s) {
+  qf_ctx* c = p->ctx;
+  const Step& st = p->steps[i];
+  const Node& nd = p->nodes[p->n + i];
+  const float2 *A, *B;
+  qf_status e = run_operand(p, st.A, row, s, &A);
+  if (e != QF_OK) return e;
+  e = run_operand(p, st.B, row, s, &B);
+  if (e != QF_OK) return e;
+  float2* C = wsp(c, nd.offset);
+  const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+  const bool timed = c->profile && st.flops == p->max_step_flops;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    e0 = take_event(c);
+    e1 = take_event(c);
+    if (e0 && e1) QF_HIP(c, hipEventRecord(e0, c->stream));
+  }
+  e = plan_gemm(p, M, N, K, A, B, C);
+  if (e != QF_OK) return e;
+  if (timed && e0 && e1) {
+    QF_HIP(c, hipEventRecord(e1, c->stream));
+    c->ev_used.push_back({e0, e1});
+    c->prof_flops += st.flops;
+    ++c->prof_launches;
+  }
+  return QF_OK;
+}
+
+static qf_status prepare(qf_plan* p) {
+  qf_ctx* c = p->ctx;
+  if (!c->ws || c->ws_bytes < p->arena_end)
+    return fail(c, QF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p->arena_end) + " bytes");
+  QF_HIP(c, hipSetDevice(c->device));
+  if (c->last_built != p || p->built_version != p->circ->version) {
+    qf_status st = build_worldlines(p);
+    if (st != QF_OK) return st;
+    c->last_built = p;
+    p->built_version = p->circ->version;
+  }
   return QF_OK;
 }
 
@@ -678,18 +781,12 @@ extern "C" qf_status qf_amplitudes(qf_plan* p, int n_batch, const uint8_t* bits_
   if (!c->ws || c->ws_bytes < p->arena_end)
     return fail(c, QF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p->arena_end) + " bytes");
   if (n_batch == 0 || s_begin == s_end) return QF_OK;
-  QF_HIP(c, hipSetDevice(c->device));
-  if (c->last_built != p || p->built_version != p->circ->version) {
-    qf_status st = build_worldlines(p);
-    if (st != QF_OK) return st;
-    c->last_built = p;
-    p->built_version = p->circ->version;
-  }
+  qf_status e = prepare(p);
+  if (e != QF_OK) return e;
   int64_t fault_after = -1;
   if (const char* f = std::getenv("QFMI_FAULT_AFTER_SLICES")) fault_after = std::atoll(f);
   const int n = p->n;
   const int k = (int)p->open.size();
-  uint32_t* amax_slots = reinterpret_cast<uint32_t*>(c->ws);  // ctx scratch: 2 slots
   int64_t done = 0;
   for (int b = 0; b < n_batch; ++b) {
     const uint8_t* row = bits_dev + (int64_t)b * n;
@@ -698,7 +795,6 @@ extern "C" qf_status qf_amplitudes(qf_plan* p, int n_batch, const uint8_t* bits_
         return fail(c, QF_ERR_INJECTED, "fault injected after " + std::to_string(done) + " slices");
       const uint64_t changed = (s == s_begin) ? ~0ull : (uint64_t)(s ^ (s - 1));
       for (size_t i = 0; i < p->steps.size(); ++i) {
-        const Step& st = p->steps[i];
         const Node& nd = p->nodes[n + i];
         bool run = (s == s_begin) || (p->flags & QF_PLAN_NO_HOIST);
         if (!run)
@@ -708,34 +804,8 @@ extern "C" qf_status qf_amplitudes(qf_plan* p, int n_batch, const uint8_t* bits_
               if (changed & mask) run = true;
             }
         if (!run) continue;
-        const float2 *A, *B;
-        qf_status e1 = run_operand(p, st.A, row, s, &A);
-        if (e1 != QF_OK) return e1;
-        e1 = run_operand(p, st.B, row, s, &B);
-        if (e1 != QF_OK) return e1;
-        float2* C = wsp(c, nd.offset);
-        const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
-        const uint32_t *amA = nullptr, *amB = nullptr;
-        if (p->precision == QF_FP16) {
-          QF_HIP(c, launch_amax(c->stream, A, M * K, amax_slots));
-          QF_HIP(c, launch_amax(c->stream, B, N * K, amax_slots + 1));
-          amA = amax_slots;
-          amB = amax_slots + 1;
-        }
-        const bool timed = c->profile && st.flops == p->max_step_flops;
-        hipEvent_t e0 = nullptr, e1v = nullptr;
-        if (timed) {
-          e0 = take_event(c);
-          e1v = take_event(c);
-          if (e0 && e1v) QF_HIP(c, hipEventRecord(e0, c->stream));
-        }
-        QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, 1, 0, 0, 0, amA, amB));
-        if (timed && e0 && e1v) {
-          QF_HIP(c, hipEventRecord(e1v, c->stream));
-          c->ev_used.push_back({e0, e1v});
-          c->prof_flops += st.flops;
-          ++c->prof_launches;
-        }
+        e = run_step(p, i, row, s);
+        if (e != QF_OK) return e;
       }
       const Node& root = p->nodes.back();
       QF_HIP(c, launch_slice_accumulate(c->stream, wsp(c, root.offset), k, p->root_pos.data(),
@@ -743,6 +813,104 @@ extern "C" qf_status qf_amplitudes(qf_plan* p, int n_batch, const uint8_t* bits_
       ++done;
     }
   }
+  return QF_OK;
+}
+
+// dst = [Y bits | X bits] from src = [X bits | Y bits] (X most significant in src)
+static void transpose_args(int xb, int yb, int conj, PermuteArgs* a) {
+  std::memset(a, 0, sizeof(*a));
+  a->nbits = xb + yb;
+  for (int i = 0; i < xb; ++i) a->perm[i] = yb + i;
+  for (int i = 0; i < yb; ++i) a->perm[xb + i] = i;
+  a->scale = 1.0f;
+  a->conj = conj;
+}
+
+// env of an operand -> env of the node it came from
+static qf_status route_env(qf_plan* p, const Operand& op, const float2* E, const uint8_t* row, int64_t s) {
+  qf_ctx* c = p->ctx;
+  const Node& nd = p->nodes[op.node];
+  PermuteArgs a;
+  if (nd.leaf) {
+    leaf_args(p, nd, op, row, s, &a);
+    float2* dst = wsp(c, p->off_envwl) + p->wl_qubits[nd.qubit].out_offset;
+    QF_HIP(c, launch_scatter_add(c->stream, E, dst, a));
+    return QF_OK;
+  }
+  std::memset(&a, 0, sizeof(a));
+  a.nbits = op.nbits;
+  a.scale = 1.0f;
+  if (op.permute) {
+    for (int i = 0; i < op.nbits; ++i) a.perm[op.perm[i]] = i;  // inverse permutation
+  } else {
+    for (int i = 0; i < op.nbits; ++i) a.perm[i] = i;
+  }
+  QF_HIP(c, launch_permute(c->stream, E, wsp(c, nd.env), a));
+  return QF_OK;
+}
+
+extern "C" qf_status qf_backward(qf_plan* p, int n_batch, const uint8_t* bits_dev, const double* cot_dev,
+                                 int64_t s_begin, int64_t s_end, float* grad_dev) {
+  if (!p) return QF_ERR_ARG;
+  qf_ctx* c = p->ctx;
+  const int64_t S = (int64_t)1 << p->total_cut_bits;
+  if (n_batch < 0 || s_begin < 0 || s_end > S || s_begin > s_end ||
+      (n_batch > 0 && (!bits_dev || !cot_dev || !grad_dev)))
+    return fail(c, QF_ERR_ARG, "qf_backward: bad arguments");
+  if (!p->backward) return fail(c, QF_ERR_UNSUPPORTED, "plan was not created with QF_PLAN_BACKWARD");
+  if (!c->ws || c->ws_bytes < p->arena_end)
+    return fail(c, QF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p->arena_end) + " bytes");
+  if (n_batch == 0 || s_begin == s_end) return QF_OK;
+  qf_status e = prepare(p);
+  if (e != QF_OK) return e;
+  QF_HIP(c, launch_zero(c->stream, c->ws + p->off_envwl, align_up(p->wl_elems * sizeof(float2))));
+  const int n = p->n;
+  const int k = (int)p->open.size();
+  const int S_steps = (int)p->steps.size();
+  float2* Q = wsp(c, p->off_bq);
+  float2* P = wsp(c, p->off_bp);
+  float2* EA = wsp(c, p->off_bea);
+  float2* EB = wsp(c, p->off_beb);
+  for (int b = 0; b < n_batch; ++b) {
+    const uint8_t* row = bits_dev + (int64_t)b * n;
+    for (int64_t s = s_begin; s < s_end; ++s) {
+      for (int i = 0; i < S_steps; ++i) {
+        e = run_step(p, (size_t)i, row, s);
+        if (e != QF_OK) return e;
+      }
+      const Node& root = p->nodes.back();
+      QF_HIP(c, launch_seed_root(c->stream, reinterpret_cast<const double2*>(cot_dev) + ((int64_t)b << k), k,
+                                 p->root_pos.data(), wsp(c, root.env)));
+      for (int i = S_steps - 1; i >= 0; --i) {
+        const Step& st = p->steps[i];
+        const float2* envC = wsp(c, p->nodes[n + i].env);
+        const float2* Aop = wsp(c, st.A.permute ? st.A.buf : p->nodes[st.A.node].offset);
+        const float2* Bop = wsp(c, st.B.permute ? st.B.buf : p->nodes[st.B.node].offset);
+        const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+        PermuteArgs a;
+        // env(A)[m][k] = sum_n env(C)[m][n] conj(B[n][k])
+        transpose_args(st.n_bits, st.k_bits, 1, &a);
+        QF_HIP(c, launch_permute(c->stream, Bop, Q, a));
+        e = plan_gemm(p, M, K, N, envC, Q, EA);
+        if (e != QF_OK) return e;
+        // env(B)[n][k] = sum_m env(C)[m][n] conj(A[m][k])
+        transpose_args(st.m_bits, st.n_bits, 0, &a);
+        QF_HIP(c, launch_permute(c->stream, envC, P, a));
+        transpose_args(st.m_bits, st.k_bits, 1, &a);
+        QF_HIP(c, launch_permute(c->stream, Aop, Q, a));
+        e = plan_gemm(p, N, K, M, P, Q, EB);
+        if (e != QF_OK) return e;
+        e = route_env(p, st.A, EA, row, s);
+        if (e != QF_OK) return e;
+        e = route_env(p, st.B, EB, row, s);
+        if (e != QF_OK) return e;
+      }
+    }
+  }
+  QF_HIP(c, launch_worldline_grad(c->stream, reinterpret_cast<const WlQubit*>(c->ws + p->off_wlq), n, p->max_nbond,
+                                  reinterpret_cast<const WlInstr*>(c->ws + p->off_prog),
+                                  reinterpret_cast<const float2*>(c->ws + p->off_gates), wsp(c, p->off_envwl),
+                                  reinterpret_cast<float2*>(grad_dev)));
   return QF_OK;
 }
 

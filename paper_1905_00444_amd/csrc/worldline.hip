@@ -8,6 +8,7 @@
 // starts at |0> and is pushed through its gate sequence; the two final components are
 // T_q[0][bonds] and T_q[1][bonds].  Arithmetic is FP64, stored as complex64.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include "qf_kernels.h"
 
 namespace qf {
@@ -85,6 +86,157 @@ hipError_t launch_slice_accumulate(hipStream_t st, const float2* root, int k, co
   unsigned blocks = (unsigned)((n + 255) / 256);
   if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(slice_accumulate_kernel, dim3(blocks), dim3(256), 0, st, root, a, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Backward of the world-line tensors: gradients of every gate entry.
+//
+// For one assignment of the bond bits, T_q[x] = (G_L ... G_1 e_0)[x] where each G_t is a one-qubit
+// gate, a projector on the bond value (q0 side of a diagonal gate) or diag(D[2k], D[2k+1]) (q1 side).
+// With lambda the environment of T_q[., bonds] (gradient in the dL/dRe + i dL/dIm convention) pulled
+// back through the later gates, and f_t the state entering gate t:
+//   one-qubit G:  grad[i][j] += lambda_i conj(f_j),   lambda <- G^H lambda
+//   diagonal D:   grad[2k+s] += lambda_s conj(f_s),   lambda_s <- conj(D[2k+s]) lambda_s
+//   projector:    lambda_{1-k} <- 0
+// Contributions are summed over all bond assignments by a block reduction and one atomic add per
+// gate and block.  States entering each gate are kept per thread (at most kMaxWlOps gates).
+constexpr int kMaxWlOps = 160;
+constexpr int kGradThreads = 128;
+
+__device__ __forceinline__ float block_sum(float v, float* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  float t = 0.f;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kGradThreads / 64; ++i) t += red[i];
+  return t;
+}
+
+__global__ void __launch_bounds__(kGradThreads)
+worldline_grad_kernel(const WlQubit* __restrict__ qubits, const WlInstr* __restrict__ prog,
+                      const float2* __restrict__ gates, const float2* __restrict__ env,
+                      float2* __restrict__ grad) {
+  __shared__ float red[kGradThreads / 64];
+  const WlQubit q = qubits[blockIdx.y];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t vol = (int64_t)1 << q.nbond;
+  if ((int64_t)blockIdx.x * blockDim.x >= vol) return;  // whole block idle (uniform)
+  const bool active = idx < vol;
+  float4 f[kMaxWlOps];
+  double v0r = 1.0, v0i = 0.0, v1r = 0.0, v1i = 0.0;
+  for (int t = 0; t < q.count; ++t) {
+    f[t] = make_float4((float)v0r, (float)v0i, (float)v1r, (float)v1i);
+    const WlInstr in = prog[q.first + t];
+    const float2* g = gates + 4 * (int64_t)in.gate;
+    if (in.kind == 1) {
+      const double a0r = g[0].x * v0r - g[0].y * v0i + g[1].x * v1r - g[1].y * v1i;
+      const double a0i = g[0].x * v0i + g[0].y * v0r + g[1].x * v1i + g[1].y * v1r;
+      const double a1r = g[2].x * v0r - g[2].y * v0i + g[3].x * v1r - g[3].y * v1i;
+      const double a1i = g[2].x * v0i + g[2].y * v0r + g[3].x * v1i + g[3].y * v1r;
+      v0r = a0r; v0i = a0i; v1r = a1r; v1i = a1i;
+    } else {
+      const int k = (int)((idx >> in.bitpos) & 1);
+      if (in.kind == 2) {
+        if (k == 0) { v1r = 0.0; v1i = 0.0; } else { v0r = 0.0; v0i = 0.0; }
+      } else {
+        const double d0r = g[2 * k].x, d0i = g[2 * k].y, d1r = g[2 * k + 1].x, d1i = g[2 * k + 1].y;
+        const double a0r = d0r * v0r - d0i * v0i, a0i = d0r * v0i + d0i * v0r;
+        const double a1r = d1r * v1r - d1i * v1i, a1i = d1r * v1i + d1i * v1r;
+        v0r = a0r; v0i = a0i; v1r = a1r; v1i = a1i;
+      }
+    }
+  }
+  double l0r = 0.0, l0i = 0.0, l1r = 0.0, l1i = 0.0;
+  if (active) {
+    const float2 e0 = env[q.out_offset + idx], e1 = env[q.out_offset + vol + idx];
+    l0r = e0.x; l0i = e0.y; l1r = e1.x; l1i = e1.y;
+  }
+  for (int t = q.count - 1; t >= 0; --t) {
+    const WlInstr in = prog[q.first + t];
+    const float2* g = gates + 4 * (int64_t)in.gate;
+    const float4 fs = f[t];
+    const double f0r = fs.x, f0i = fs.y, f1r = fs.z, f1i = fs.w;
+    double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // 4 complex contributions
+    if (in.kind == 1) {
+      // c[2i + j] = lambda_i conj(f_j)
+      c[0] = l0r * f0r + l0i * f0i; c[1] = l0i * f0r - l0r * f0i;
+      c[2] = l0r * f1r + l0i * f1i; c[3] = l0i * f1r - l0r * f1i;
+      c[4] = l1r * f0r + l1i * f0i; c[5] = l1i * f0r - l1r * f0i;
+      c[6] = l1r * f1r + l1i * f1i; c[7] = l1i * f1r - l1r * f1i;
+      // lambda_j <- sum_i conj(G[i][j]) lambda_i
+      const double n0r = g[0].x * l0r + g[0].y * l0i + g[2].x * l1r + g[2].y * l1i;
+      const double n0i = g[0].x * l0i - g[0].y * l0r + g[2].x * l1i - g[2].y * l1r;
+      const double n1r = g[1].x * l0r + g[1].y * l0i + g[3].x * l1r + g[3].y * l1i;
+      const double n1i = g[1].x * l0i - g[1].y * l0r + g[3].x * l1i - g[3].y * l1r;
+      l0r = n0r; l0i = n0i; l1r = n1r; l1i = n1i;
+    } else {
+      const int k = (int)((idx >> in.bitpos) & 1);
+      if (in.kind == 2) {
+        if (k == 0) { l1r = 0.0; l1i = 0.0; } else { l0r = 0.0; l0i = 0.0; }
+      } else {
+        c[4 * k + 0] = l0r * f0r + l0i * f0i; c[4 * k + 1] = l0i * f0r - l0r * f0i;
+        c[4 * k + 2] = l1r * f1r + l1i * f1i; c[4 * k + 3] = l1i * f1r - l1r * f1i;
+        const double d0r = g[2 * k].x, d0i = g[2 * k].y, d1r = g[2 * k + 1].x, d1i = g[2 * k + 1].y;
+        const double n0r = d0r * l0r + d0i * l0i, n0i = d0r * l0i - d0i * l0r;
+        const double n1r = d1r * l1r + d1i * l1i, n1i = d1r * l1i - d1i * l1r;
+        l0r = n0r; l0i = n0i; l1r = n1r; l1i = n1i;
+      }
+    }
+    if (in.kind != 2) {
+      float* out = reinterpret_cast<float*>(grad + 4 * (int64_t)in.out);
+      for (int e = 0; e < 8; ++e) {
+        const float s = block_sum(active ? (float)c[e] : 0.f, red);
+        if (threadIdx.x == 0 && s != 0.f) atomicAdd(out + e, s);
+      }
+    }
+  }
+}
+
+hipError_t launch_worldline_grad(hipStream_t st, const WlQubit* qubits, int n_qubits, int max_nbond,
+                                 const WlInstr* prog, const float2* gates, const float2* env, float2* grad) {
+  const int64_t vol = (int64_t)1 << max_nbond;
+  dim3 grid((unsigned)((vol + kGradThreads - 1) / kGradThreads), (unsigned)n_qubits);
+  hipLaunchKernelGGL(worldline_grad_kernel, grid, dim3(kGradThreads), 0, st, qubits, prog, gates, env, grad);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256)
+seed_root_kernel(const double2* __restrict__ cot, AccArgs a, float2* __restrict__ env_root) {
+  const int64_t n = (int64_t)1 << a.k;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    int64_t dst = 0;
+    for (int t = 0; t < a.k; ++t) dst |= ((j >> t) & 1) << a.pos[t];
+    const double2 c = cot[j];
+    env_root[dst] = make_float2((float)c.x, (float)c.y);
+  }
+}
+
+hipError_t launch_seed_root(hipStream_t st, const double2* cot, int k, const int* pos, float2* env_root) {
+  AccArgs a;
+  a.k = k;
+  for (int t = 0; t < 32; ++t) a.pos[t] = t < k ? pos[t] : 0;
+  const int64_t n = (int64_t)1 << k;
+  unsigned blocks = (unsigned)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(seed_root_kernel, dim3(blocks), dim3(256), 0, st, cot, a, env_root);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) zero_kernel(uint4* __restrict__ p, int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Clears `bytes` (a multiple of 16, 16-byte aligned) with a kernel, so it may sit in a captured graph.
+hipError_t launch_zero(hipStream_t st, void* p, size_t bytes) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return hipSuccess;
+  unsigned blocks = (unsigned)std::min<int64_t>((n16 + 255) / 256, 8192);
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(p), n16);
   return hipGetLastError();
 }
 

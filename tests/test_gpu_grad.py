@@ -1,0 +1,140 @@
+"""Backward pass (environment tensors through the contraction tree, then through every
+world-line) against the FP64 adjoint state-vector gradient and exact finite differences."""
+import numpy as np
+import pytest
+
+from oracle import grad as ograd
+from oracle import sv
+from oracle.metrics import rel_err
+from oracle.parse import read_circuit
+from workloads.bitstrings import random_bitstrings
+from workloads.circuits import generate
+from workloads.plans import sweep_plan, region_plan
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1905_00444_amd import Context
+    assert torch.cuda.is_available()
+    return Context(0)
+
+
+def _oracle_grad(text, bits_full, cot_full):
+    g = ograd.adjoint_gradient(read_circuit(text), bits_full, cot_full)
+    return np.stack([np.asarray(x).reshape(4) for x in g])
+
+
+def _expand_open(bits, open_q, cot):
+    """Prefix rows x 2^k completions -> full bitstrings and their cotangents."""
+    k = len(open_q)
+    rows, cots = [], []
+    for b in range(bits.shape[0]):
+        for j in range(2 ** k):
+            r = bits[b].copy()
+            for t, q in enumerate(open_q):
+                r[q] = (j >> (k - 1 - t)) & 1
+            rows.append(r)
+            cots.append(cot[b, j])
+    return np.array(rows, dtype=np.uint8), np.array(cots)
+
+
+def test_grad_4x4_d16_norm_loss_vs_adjoint_oracle(ctx):
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    _say("grad 4x4 d16")
+    c = generate(4, 4, 16, 0)
+    text = c.to_text()
+    bits = random_bitstrings(16, 16, 1)
+    p = Plan(ctx, Circuit(ctx, text), sweep_plan(c), "fp32", backward=True)
+    a = p.amplitudes(bits)
+    g = p.backward(bits, 2 * a)
+    torch.cuda.synchronize()
+    ref = _oracle_grad(text, bits, 2 * sv.amplitudes(text, bits))
+    assert rel_err(g.cpu().numpy(), ref) <= 1e-4
+
+
+def test_grad_4x5_d32_cuts_open_random_cotangent(ctx):
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    _say("grad 4x5 d32 cuts + open")
+    c = generate(4, 5, 32, 2)
+    text = c.to_text()
+    qid = c.qubit_of()
+    cuts = [[qid[(1, 3)], qid[(2, 3)], 0, 2], [qid[(3, 1)], qid[(3, 2)], 1, 1]]
+    plan, _ = region_plan(c, 2, 2, cuts, [(3, 4), (2, 4)])
+    bits = random_bitstrings(3, 20, 7)
+    rng = np.random.default_rng(3)
+    cot = rng.normal(size=(3, 4)) + 1j * rng.normal(size=(3, 4))
+    p = Plan(ctx, Circuit(ctx, text), plan, "fp32", backward=True)
+    g = p.backward(bits, cot)
+    torch.cuda.synchronize()
+    fb, fc = _expand_open(bits, plan["open"], cot)
+    ref = _oracle_grad(text, fb, fc)
+    assert rel_err(g.cpu().numpy(), ref) <= 1e-4
+
+
+def test_grad_6x6_d24_64_bitstrings_exact_finite_differences(ctx):
+    """L = sum_b |a_b|^2 is quadratic in each gate entry: central differences are exact."""
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    _say("grad 6x6 d24 vs finite differences")
+    c = generate(6, 6, 24, 0)
+    text = c.to_text()
+    bits = random_bitstrings(64, 36, 1)
+    circ = Circuit(ctx, text)
+    plan = sweep_plan(c)
+    p = Plan(ctx, circ, plan, "fp32", backward=True)
+    a = p.amplitudes(bits)
+    g = p.backward(bits, 2 * a).cpu().numpy()
+    base = circ.values.copy()
+
+    def loss(vals):
+        circ.set_values(vals)
+        out = p.amplitudes(bits)
+        torch.cuda.synchronize()
+        return float(torch.sum(torch.abs(out) ** 2).item())
+
+    ops = circ.ops
+    two = [i for i, (_, _, qs) in enumerate(ops) if len(qs) == 2]
+    one = [i for i, (_, _, qs) in enumerate(ops) if len(qs) == 1]
+    picks = [(two[5], 3), (two[-7], 1), (one[3], 2), (one[len(one) // 2], 0), (one[-1], 1)]
+    h = 0.5
+    for i, e in picks:
+        fd = 0j
+        for step, w in ((h, 1.0), (1j * h, 1j)):
+            vp, vm = base.copy(), base.copy()
+            vp[i, e] += step
+            vm[i, e] -= step
+            fd += w * (loss(vp) - loss(vm)) / (2 * h)
+        scale = np.max(np.abs(g))
+        assert abs(g[i, e] - fd) <= 2e-4 * scale, (i, e, g[i, e], fd)
+    circ.set_values(base)
+
+
+def test_autograd_function_matches_direct_backward(ctx):
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    from paper_1905_00444_amd.autograd import QFlexAmplitudes
+    _say("autograd.Function")
+    c = generate(3, 4, 16, 4)
+    text = c.to_text()
+    bits = random_bitstrings(8, 12, 2)
+    circ = Circuit(ctx, text)
+    p = Plan(ctx, circ, sweep_plan(c, open_qubits=[11]), "fp32", backward=True)
+    vals = torch.tensor(circ.values, dtype=torch.complex64, device="cuda", requires_grad=True)
+    amps = QFlexAmplitudes.apply(vals, p, bits)
+    loss = (amps.abs() ** 2).sum()
+    loss.backward()
+    direct = p.backward(bits, 2 * amps.detach())
+    torch.cuda.synchronize()
+    assert torch.allclose(vals.grad, direct, rtol=0, atol=1e-6 * float(direct.abs().max()))
+    fb, fc = _expand_open(bits, [11], 2 * amps.detach().cpu().numpy())
+    ref = _oracle_grad(text, fb, fc)
+    assert rel_err(vals.grad.cpu().numpy(), ref) <= 1e-4
