@@ -27,6 +27,7 @@
 // and rasterised in groups of row-tiles for L2 reuse.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include "qf_kernels.h"
 
 namespace qf {
@@ -265,6 +266,189 @@ cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
     }
 }
 
+// Large shapes, BF16-family products: 512 threads = 8 waves as 4 (M) x 2 (N); a wave owns
+// 4 x 8 MFMA tiles (64 rows x 64 complex columns); block tile 256 rows x 128 complex columns;
+// K-tiles of 16 complex (one 16x16x32 MFMA step).  Two LDS stages: while the MFMAs consume one
+// stage, the next K-tile (already in registers) is converted and stored into the other, and the
+// K-tile after it is fetched from global memory; one barrier per K-tile.  LDS rows are 16
+// complex (64 B per plane) padded to 80 B, which spreads the 16-byte reads of 16 consecutive
+// rows over all banks.
+constexpr int kV2Threads = 512;
+constexpr int kV2BM = 256, kV2BN = 128, kV2BK = 16;
+constexpr int kV2Row = 80;                      // bytes per LDS row (64 + 16 pad)
+constexpr int kV2PlaneA = kV2BM * kV2Row;       // 20 KiB
+constexpr int kV2PlaneB = kV2BN * kV2Row;       // 10 KiB
+
+template <int PREC>
+struct V2 {
+  static constexpr int planes = PREC == P_BF16X3 ? 2 : 1;
+  static constexpr int stage = planes * (kV2PlaneA + kV2PlaneB);
+};
+
+template <int PREC>
+__device__ __forceinline__ void v2_store(char* st, const float4 (&ra)[4], const float4 (&rb)[2], float sa, float sb) {
+  const int tid = threadIdx.x;
+  constexpr int planes = V2<PREC>::planes;
+  char* A = st;
+  char* B = st + planes * kV2PlaneA;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = (tid >> 3) + 64 * i, c = tid & 7;  // c: complex pair 2c, 2c+1
+    const float4 v = ra[i];
+    char* dst = A + row * kV2Row + c * 8;
+    if constexpr (PREC == P_BF16X3) {
+      const uint32_t h0 = pack_bf16x2(v.x, v.y), h1 = pack_bf16x2(v.z, v.w);
+      const uint32_t l0 = pack_bf16x2(v.x - bf16_lo_to_f32(h0), v.y - bf16_hi_to_f32(h0));
+      const uint32_t l1 = pack_bf16x2(v.z - bf16_lo_to_f32(h1), v.w - bf16_hi_to_f32(h1));
+      *reinterpret_cast<uint2*>(dst) = make_uint2(h0, h1);
+      *reinterpret_cast<uint2*>(dst + kV2PlaneA) = make_uint2(l0, l1);
+    } else {
+      *reinterpret_cast<uint2*>(dst) = make_uint2(pack_f16x2(v.x * sa, v.y * sa), pack_f16x2(v.z * sa, v.w * sa));
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int row = (tid >> 3) + 64 * i, c = tid & 7;
+    const float4 v = rb[i];
+    char* dst = B + row * kV2Row + c * 8;
+    if constexpr (PREC == P_BF16X3) {
+      const uint32_t h0 = pack_bf16x2(v.x, v.y), h1 = pack_bf16x2(v.z, v.w);
+      const uint32_t l0 = pack_bf16x2(v.x - bf16_lo_to_f32(h0), v.y - bf16_hi_to_f32(h0));
+      const uint32_t l1 = pack_bf16x2(v.z - bf16_lo_to_f32(h1), v.w - bf16_hi_to_f32(h1));
+      *reinterpret_cast<uint2*>(dst) = make_uint2(h0, h1);
+      *reinterpret_cast<uint2*>(dst + kV2PlaneB) = make_uint2(l0, l1);
+    } else {
+      *reinterpret_cast<uint2*>(dst) = make_uint2(pack_f16x2(v.x * sb, v.y * sb), pack_f16x2(v.z * sb, v.w * sb));
+    }
+  }
+}
+
+__device__ __forceinline__ void v2_load(float4 (&ra)[4], float4 (&rb)[2], const float2* __restrict__ A,
+                                        const float2* __restrict__ B, int64_t K, int64_t k0) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = (tid >> 3) + 64 * i, c = tid & 7;
+    ra[i] = *reinterpret_cast<const float4*>(A + row * K + k0 + 2 * c);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int row = (tid >> 3) + 64 * i, c = tid & 7;
+    rb[i] = *reinterpret_cast<const float4*>(B + row * K + k0 + 2 * c);
+  }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(kV2Threads)
+cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
+         float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, const uint32_t* amaxA, const uint32_t* amaxB) {
+  __shared__ __attribute__((aligned(16))) char lds[2 * V2<PREC>::stage];
+  constexpr int planes = V2<PREC>::planes;
+
+  const int64_t tiles_m = M / kV2BM, tiles_n = N / kV2BN;
+  const int64_t ntiles = tiles_m * tiles_n;
+  int64_t bid = blockIdx.x;
+  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  const int64_t group = 8;
+  const int64_t per_group = group * tiles_n;
+  const int64_t gidx = bid / per_group;
+  const int64_t first_m = gidx * group;
+  const int64_t gsize = (tiles_m - first_m) < group ? (tiles_m - first_m) : group;
+  const int64_t tm = first_m + (bid % per_group) % gsize;
+  const int64_t tn = (bid % per_group) / gsize;
+
+  const int64_t batch = blockIdx.z;
+  A += batch * sa + tm * kV2BM * K;
+  B += batch * sb + tn * kV2BN * K;
+  C += batch * sc;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 64;  // first row of the wave
+  const int wc = (wave & 1) * 64;   // first complex column of the wave
+  const int l16 = lane & 15, lg = lane >> 4, q = l16 & 1;
+
+  float scale_a = 1.f, scale_b = 1.f, unscale = 1.f;
+  if constexpr (PREC == P_FP16) {
+    const int s_a = fp16_shift(amaxA), s_b = fp16_shift(amaxB);
+    scale_a = ldexpf(1.f, s_a);
+    scale_b = ldexpf(1.f, s_b);
+    unscale = ldexpf(1.f, -(s_a + s_b));
+  }
+
+  f4 acc[4][8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+
+  float4 ra[4], rb[2];
+  const int64_t nk = K / kV2BK;
+  v2_load(ra, rb, A, B, K, 0);
+  v2_store<PREC>(lds, ra, rb, scale_a, scale_b);
+  if (nk > 1) v2_load(ra, rb, A, B, K, kV2BK);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const char* st = lds + (kt & 1) * V2<PREC>::stage;
+    const char* LA = st;
+    const char* LB = st + planes * kV2PlaneA;
+    u4 ah[4], al[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const char* p = LA + (wr + 16 * i + l16) * kV2Row + lg * 16;
+      ah[i] = *reinterpret_cast<const u4*>(p);
+      if constexpr (PREC == P_BF16X3) al[i] = *reinterpret_cast<const u4*>(p + kV2PlaneA);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const char* p = LB + (wc + 8 * j + (l16 >> 1)) * kV2Row + lg * 16;
+      u4 bh = *reinterpret_cast<const u4*>(p);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bh[e] = bexpand16(bh[e], q);
+      if constexpr (PREC == P_BF16X3) {
+        u4 bl = *reinterpret_cast<const u4*>(p + kV2PlaneB);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bl[e] = bexpand16(bl[e], q);
+        const bf8 vbh = __builtin_bit_cast(bf8, bh), vbl = __builtin_bit_cast(bf8, bl);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, al[i]), vbh, acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), vbl, acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), vbh, acc[i][j], 0, 0, 0);
+      } else {
+        const h8 vb = __builtin_bit_cast(h8, bh);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, ah[i]), vb, acc[i][j], 0, 0, 0);
+      }
+    }
+    if (kt + 1 < nk) {
+      v2_store<PREC>(lds + ((kt + 1) & 1) * V2<PREC>::stage, ra, rb, scale_a, scale_b);
+      if (kt + 2 < nk) v2_load(ra, rb, A, B, K, (kt + 2) * kV2BK);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const f4 v = acc[i][j] * unscale;
+      const float s0 = q ? v[0] : v[2], s1 = q ? v[1] : v[3];
+      const float r0 = __shfl_xor(s0, 1), r1 = __shfl_xor(s1, 1);
+      const int64_t row = tm * kV2BM + wr + 16 * i + 4 * lg + (q ? 2 : 0);
+      const int64_t col = tn * kV2BN + wc + 8 * j + (l16 >> 1);
+      float2 o0, o1;
+      if (q) { o0 = make_float2(r0, v[2]); o1 = make_float2(r1, v[3]); }
+      else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
+      C[row * N + col] = o0;
+      C[(row + 1) * N + col] = o1;
+    }
+}
+
 // Small or thin shapes: one thread per output element, FP32 complex FMA over K.
 __global__ void __launch_bounds__(256)
 cgemm_simt(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
@@ -302,10 +486,29 @@ static hipError_t launch_tiled(hipStream_t st, int64_t M, int64_t N, int64_t K, 
   return hipGetLastError();
 }
 
+static int g_gemm_variant = -1;  // -1: not read yet; 0: v1 tiles only; 1: large-tile kernel where it fits
+
+static bool use_v2() {
+  if (g_gemm_variant < 0) {
+    const char* e = getenv("QFMI_GEMM_V1");
+    g_gemm_variant = (e && e[0] == '1') ? 0 : 1;
+  }
+  return g_gemm_variant == 1;
+}
+
 template <int PREC>
 static hipError_t dispatch(hipStream_t st, int64_t M, int64_t N, int64_t K, const float2* A, const float2* B,
                            float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
                            const uint32_t* amaxA, const uint32_t* amaxB) {
+  if constexpr (PREC != P_FP32) {
+    if (use_v2() && M >= kV2BM && N >= kV2BN && K >= kV2BK) {
+      const int64_t tiles = (M / kV2BM) * (N / kV2BN);
+      hipLaunchKernelGGL((cgemm_v2<PREC>), dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kV2Threads), 0, st,
+                         M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB);
+      return hipGetLastError();
+    }
+  }
+  if (K < kBK) return hipErrorInvalidValue;
   if (M >= 128 && N >= 64) return launch_tiled<PREC, 4, 4>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
   if (M >= 64 && N >= 32) return launch_tiled<PREC, 2, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
   return launch_tiled<PREC, 1, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
@@ -316,7 +519,9 @@ static bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
                            const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
                            const uint32_t* amaxA, const uint32_t* amaxB) {
-  const bool tiled = pow2(M) && pow2(N) && pow2(K) && M >= 32 && N >= 32 && K >= kBK;
+  const bool p2 = pow2(M) && pow2(N) && pow2(K);
+  const bool big = p2 && precision != P_FP32 && use_v2() && M >= kV2BM && N >= kV2BN && K >= kV2BK;
+  const bool tiled = big || (p2 && M >= 32 && N >= 32 && K >= kBK);
   if (!tiled) {
     const int64_t total = M * N;
     unsigned blocks = (unsigned)((total + 255) / 256);
