@@ -74,8 +74,10 @@ typedef struct {
 enum {
   QF_PLAN_NO_HOIST = 1, /* recompute every step for every slice (no reuse of slice-independent
                            subtrees across slices) */
-  QF_PLAN_BACKWARD = 2  /* keep every forward tensor and reserve environment buffers so that
+  QF_PLAN_BACKWARD = 2, /* keep every forward tensor and reserve environment buffers so that
                            qf_backward can run (implies QF_PLAN_NO_HOIST; larger workspace) */
+  QF_PLAN_GRAPH = 4     /* batched plans: capture one group's launches in a hipGraph and replay it
+                           for every group (needs a non-null stream) */
 };
 
 /* Contraction plan.  steps: 2*n_steps node ids (lhs, rhs) in execution order.  Ids 0..n-1
@@ -91,6 +93,10 @@ typedef struct {
   const int32_t* open;
   int32_t precision; /* qf_precision */
   int32_t flags;     /* QF_PLAN_* */
+  int32_t batch;     /* chains (bitstring x slice pairs) per launch: 0 or 1 runs chains one by
+                        one with reuse of slice-independent subtrees; a power of two G > 1 runs
+                        G chains through every step as one batched launch (no reuse; every
+                        buffer is G times larger).  Identical results either way. */
 } qf_plan_desc;
 
 typedef struct {

@@ -15,6 +15,7 @@ QF_FP32, QF_BF16X3, QF_FP16 = 0, 1, 2
 QF_OP_1Q, QF_OP_2Q_DIAG = 1, 2
 QF_PLAN_NO_HOIST = 1
 QF_PLAN_BACKWARD = 2
+QF_PLAN_GRAPH = 4
 
 STATUS_NAMES = {0: "QF_OK", -1: "QF_ERR_ARG", -2: "QF_ERR_PLAN", -3: "QF_ERR_WORKSPACE", -4: "QF_ERR_HIP",
                 -5: "QF_ERR_UNSUPPORTED", -6: "QF_ERR_INJECTED"}
@@ -32,7 +33,7 @@ class qf_cut(C.Structure):
 class qf_plan_desc(C.Structure):
     _fields_ = [("n_steps", C.c_int32), ("steps", C.POINTER(C.c_int32)), ("n_cuts", C.c_int32),
                 ("cuts", C.POINTER(qf_cut)), ("n_open", C.c_int32), ("open", C.POINTER(C.c_int32)),
-                ("precision", C.c_int32), ("flags", C.c_int32)]
+                ("precision", C.c_int32), ("flags", C.c_int32), ("batch", C.c_int32)]
 
 
 class qf_plan_info(C.Structure):

@@ -134,7 +134,7 @@ class Circuit:
 
 class Plan:
     def __init__(self, ctx: Context, circuit: Circuit, plan: dict, precision: str = "fp32", hoist: bool = True,
-                 backward: bool = False):
+                 backward: bool = False, batch: int = 1, graph: bool = False):
         self.ctx = ctx
         self.circuit = circuit
         self.plan = plan
@@ -154,7 +154,9 @@ class Plan:
         d.n_open = len(opn)
         d.open = opn.ctypes.data_as(C.POINTER(C.c_int32)) if len(opn) else None
         d.precision = PRECISIONS[precision]
-        d.flags = (0 if hoist else _lib.QF_PLAN_NO_HOIST) | (_lib.QF_PLAN_BACKWARD if backward else 0)
+        d.flags = ((0 if hoist else _lib.QF_PLAN_NO_HOIST) | (_lib.QF_PLAN_BACKWARD if backward else 0)
+                   | (_lib.QF_PLAN_GRAPH if graph else 0))
+        d.batch = int(batch)
         h = C.c_void_p()
         check(ctx.lib.qf_plan_create(ctx.h, circuit.h, C.byref(d), C.byref(h)), ctx.h)
         self.h = h
@@ -173,20 +175,21 @@ class Plan:
 
     def amplitudes(self, bits, s_begin: int = 0, s_end: Optional[int] = None, out=None):
         """Amplitudes (n_batch, 2^n_open) complex128 on the device, summed over slices
-        [s_begin, s_end) and added into `out` if given."""
+        [s_begin, s_end) and added into `out` if given.  Everything is enqueued on the
+        context's stream."""
         torch = _torch()
         info = self.info()
         if s_end is None:
             s_end = info["n_slices"]
         self.ctx.ensure_workspace(info["workspace_bytes"])
-        if isinstance(bits, np.ndarray):
-            bits_t = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint8)).to(self.ctx.device)
-        else:
-            bits_t = bits.to(device=self.ctx.device, dtype=torch.uint8).contiguous()
-        nb = bits_t.shape[0]
-        if out is None:
-            out = torch.zeros((nb, 2 ** self.n_open), dtype=torch.complex128, device=self.ctx.device)
         with torch.cuda.stream(self.ctx.stream):
+            if isinstance(bits, np.ndarray):
+                bits_t = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint8)).to(self.ctx.device)
+            else:
+                bits_t = bits.to(device=self.ctx.device, dtype=torch.uint8).contiguous()
+            nb = bits_t.shape[0]
+            if out is None:
+                out = torch.zeros((nb, 2 ** self.n_open), dtype=torch.complex128, device=self.ctx.device)
             st = self.ctx.lib.qf_amplitudes(self.h, nb, C.c_void_p(bits_t.data_ptr()), int(s_begin), int(s_end),
                                             C.c_void_p(out.data_ptr()))
         self._bits_keepalive = bits_t
@@ -201,15 +204,15 @@ class Plan:
         if s_end is None:
             s_end = info["n_slices"]
         self.ctx.ensure_workspace(info["workspace_bytes"])
-        if isinstance(bits, np.ndarray):
-            bits_t = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint8)).to(self.ctx.device)
-        else:
-            bits_t = bits.to(device=self.ctx.device, dtype=torch.uint8).contiguous()
-        cot_t = torch.as_tensor(cot).to(device=self.ctx.device, dtype=torch.complex128).contiguous()
-        assert cot_t.shape == (bits_t.shape[0], 2 ** self.n_open)
-        if grad is None:
-            grad = torch.zeros((len(self.circuit.ops), 4), dtype=torch.complex64, device=self.ctx.device)
         with torch.cuda.stream(self.ctx.stream):
+            if isinstance(bits, np.ndarray):
+                bits_t = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint8)).to(self.ctx.device)
+            else:
+                bits_t = bits.to(device=self.ctx.device, dtype=torch.uint8).contiguous()
+            cot_t = torch.as_tensor(cot).to(device=self.ctx.device, dtype=torch.complex128).contiguous()
+            assert cot_t.shape == (bits_t.shape[0], 2 ** self.n_open)
+            if grad is None:
+                grad = torch.zeros((len(self.circuit.ops), 4), dtype=torch.complex64, device=self.ctx.device)
             st = self.ctx.lib.qf_backward(self.h, bits_t.shape[0], C.c_void_p(bits_t.data_ptr()),
                                           C.c_void_p(cot_t.data_ptr()), int(s_begin), int(s_end),
                                           C.c_void_p(grad.data_ptr()))

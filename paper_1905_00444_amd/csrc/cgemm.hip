@@ -475,6 +475,39 @@ cgemm_simt(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
   }
 }
 
+// Few outputs, long K (e.g. the last contraction of two halves into a scalar): one workgroup
+// per output element, threads stride over K, then a workgroup reduction.
+__global__ void __launch_bounds__(256)
+cgemm_splitk(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
+             float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc) {
+  __shared__ float red[2][4];
+  const int64_t batch = blockIdx.z;
+  const int64_t out = blockIdx.x;  // m * N + n
+  const int64_t m = out / N, n = out - m * N;
+  const float2* a = A + batch * sa + m * K;
+  const float2* b = B + batch * sb + n * K;
+  float cr = 0.f, ci = 0.f;
+  for (int64_t k = threadIdx.x; k < K; k += 256) {
+    const float2 x = a[k], y = b[k];
+    cr = fmaf(x.x, y.x, cr);
+    cr = fmaf(-x.y, y.y, cr);
+    ci = fmaf(x.x, y.y, ci);
+    ci = fmaf(x.y, y.x, ci);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    cr += __shfl_xor(cr, off);
+    ci += __shfl_xor(ci, off);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[0][w] = cr; red[1][w] = ci; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float r = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const float i = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    C[batch * sc + out] = make_float2(r, i);
+  }
+}
+
 template <int PREC, int WTM, int WTN>
 static hipError_t launch_tiled(hipStream_t st, int64_t M, int64_t N, int64_t K, const float2* A,
                                const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb,
@@ -522,6 +555,11 @@ hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, 
   const bool p2 = pow2(M) && pow2(N) && pow2(K);
   const bool big = p2 && precision != P_FP32 && use_v2() && M >= kV2BM && N >= kV2BN && K >= kV2BK;
   const bool tiled = big || (p2 && M >= 32 && N >= 32 && K >= kBK);
+  if (!tiled && M * N <= 4096 && K >= 256) {
+    hipLaunchKernelGGL(cgemm_splitk, dim3((unsigned)(M * N), 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C,
+                       sa, sb, sc);
+    return hipGetLastError();
+  }
   if (!tiled) {
     const int64_t total = M * N;
     unsigned blocks = (unsigned)((total + 255) / 256);

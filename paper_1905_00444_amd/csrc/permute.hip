@@ -35,6 +35,9 @@ struct PermKernelArgs {
   const uint8_t* dyn_bits;
   int64_t dyn_stride;
   float conj_sign;          // -1 to conjugate
+  int64_t src_bstride, dst_bstride;
+  const int64_t* base_table;
+  int base_stride;
 };
 
 __device__ __forceinline__ int lds_index(int u) { return u + (u >> 5); }
@@ -43,8 +46,12 @@ __global__ void __launch_bounds__(kPermThreads)
 permute_kernel(const float2* __restrict__ src, float2* __restrict__ dst, PermKernelArgs a) {
   extern __shared__ float2 tile[];
   const int64_t g = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+  const int64_t z = blockIdx.z;
+  src += z * a.src_bstride;
+  dst += z * a.dst_bstride;
   int64_t sbase = a.src_base, dbase = 0;
   if (a.dyn_bits) sbase += (int64_t)(a.dyn_bits[0] & 1) * a.dyn_stride;
+  if (a.base_table) sbase += a.base_table[z * a.base_stride];
   for (int i = 0; i < a.n_outer; ++i) {
     const int64_t bit = (g >> i) & 1;
     sbase += bit << a.o_src[i];
@@ -110,11 +117,16 @@ hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const 
   a.dyn_bits = p.dyn_bits;
   a.dyn_stride = p.dyn_stride;
   a.conj_sign = p.conj ? -1.f : 1.f;
+  a.src_bstride = p.src_bstride;
+  a.dst_bstride = p.dst_bstride;
+  a.base_table = p.base_table;
+  a.base_stride = p.base_stride;
   const int64_t tiles = (int64_t)1 << no;
   const unsigned gx = (unsigned)std::min<int64_t>(tiles, 65536);
   const unsigned gy = (unsigned)(tiles / gx);
   const size_t lds = (size_t)((1 << t) + (1 << t) / 32 + 1) * sizeof(float2);
-  hipLaunchKernelGGL(permute_kernel, dim3(gx, gy), dim3(kPermThreads), lds, st, src, dst, a);
+  hipLaunchKernelGGL(permute_kernel, dim3(gx, gy, (unsigned)std::max(1, p.batch)), dim3(kPermThreads), lds, st,
+                     src, dst, a);
   return hipGetLastError();
 }
 

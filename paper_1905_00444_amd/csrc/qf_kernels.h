@@ -36,6 +36,12 @@ struct PermuteArgs {
   const uint8_t* dyn_bits;
   int64_t dyn_stride;
   int conj;  // conjugate while copying
+  // batched launches (grid z = batch): per-batch source/destination strides, and an optional
+  // table of per-batch source base offsets base_table[z * base_stride]
+  int batch = 1;
+  int64_t src_bstride = 0, dst_bstride = 0;
+  const int64_t* base_table = nullptr;
+  int base_stride = 0;
 };
 hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& a);
 
@@ -51,6 +57,29 @@ hipError_t launch_worldline_grad(hipStream_t st, const WlQubit* qubits, int n_qu
 hipError_t launch_seed_root(hipStream_t st, const double2* cot, int k, const int* pos, float2* env_root);
 
 hipError_t launch_zero(hipStream_t st, void* p, size_t bytes);
+
+// Per-leaf description of the bits fixed per chain (a chain is one bitstring x one slice).
+constexpr int kMaxLeafCut = 24;
+struct LeafDesc {
+  int32_t n_cut;                 // fixed cut bits of this world-line
+  int32_t xpos;                  // bit position of the output bit, -1 if the qubit is open
+  int32_t qubit;
+  int32_t pad;
+  int32_t shift[kMaxLeafCut];    // bit of the slice id
+  int32_t pos[kMaxLeafCut];      // bit position in the world-line
+};
+
+// For chains c = *chain0 + g (g < G): b = c / s_range, s = s_begin + c % s_range;
+// base_table[g * n_leaves + l] = world-line offset of leaf l's fixed bits; chain_b[g] = b
+// (-1 past n_chains).
+hipError_t launch_chain_setup(hipStream_t st, const int64_t* chain0, int G, int n_leaves, const LeafDesc* leaves,
+                              const uint8_t* bits, int n_qubits, int64_t s_begin, int64_t s_range, int64_t n_chains,
+                              int64_t* base_table, int32_t* chain_b);
+// out[chain_b[g]][j] += root[g][sum_t bit_t(j) << pos[t]] for g = 0..G-1 in order (FP64).
+hipError_t launch_slice_accumulate_batched(hipStream_t st, const float2* root, int k, const int* pos, int G,
+                                           const int32_t* chain_b, double2* out);
+// *chain0 = value (add = 0) or *chain0 += value (add = 1), as a kernel (graph-capturable).
+hipError_t launch_chain_counter(hipStream_t st, int64_t* chain0, int64_t value, int add);
 
 // Batched complex GEMM, C[m][n] = sum_k A[m][k] B[n][k].
 hipError_t launch_cgemm(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K,

@@ -133,6 +133,14 @@ struct qf_plan {
   double max_step_flops = 0.0;
   // arena (offsets relative to the workspace start)
   size_t off_gates = 0, off_wlq = 0, off_prog = 0, off_wl = 0, arena_end = 0;
+  // batched plans: G chains per launch
+  int G = 1;
+  bool graph = false;
+  std::vector<LeafDesc> leaf_desc;
+  size_t off_leafdesc = 0, off_btable = 0, off_chainb = 0;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph_obj = nullptr;
+  std::vector<int64_t> graph_key;
   // backward plans: world-line environments and per-step scratch
   bool backward = false;
   size_t wl_elems = 0;
@@ -282,6 +290,11 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   p->flags = d->flags;
   p->backward = (d->flags & QF_PLAN_BACKWARD) != 0;
   if (p->backward) p->flags |= QF_PLAN_NO_HOIST;
+  p->G = d->batch > 1 ? d->batch : 1;
+  if (p->G & (p->G - 1)) return fail(ctx, QF_ERR_ARG, "batch must be a power of two");
+  if (p->G > 1 && p->backward) return fail(ctx, QF_ERR_UNSUPPORTED, "backward plans run chains one at a time");
+  if (p->G > 1) p->flags |= QF_PLAN_NO_HOIST;
+  p->graph = p->G > 1 && (d->flags & QF_PLAN_GRAPH);
 
   // ---- bonds: one bit per diagonal two-qubit gate, time order (ops are sorted by cycle)
   std::vector<std::vector<int>> edge_gate_bits;  // per edge: op indices
@@ -401,6 +414,24 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
       else nd.labels.push_back(lab);
     }
   }
+  // per-leaf fixed bits (batched chains compute their offsets on the device)
+  p->leaf_desc.assign(n, LeafDesc());
+  for (int q = 0; q < n; ++q) {
+    LeafDesc& ld = p->leaf_desc[q];
+    std::memset(&ld, 0, sizeof(ld));
+    const auto& full = p->leaf_full_labels[q];
+    const int hb = (int)full.size();
+    ld.qubit = q;
+    ld.xpos = contains(p->open, q) ? -1 : hb - 1;
+    for (int j = 1; j < hb; ++j) {
+      const int lab = full[j];
+      if (p->label_cut[lab] < 0) continue;
+      if (ld.n_cut >= kMaxLeafCut) return fail(ctx, QF_ERR_UNSUPPORTED, "too many cut bits on one world-line");
+      ld.shift[ld.n_cut] = p->label_cut_shift[lab];
+      ld.pos[ld.n_cut] = hb - 1 - j;
+      ++ld.n_cut;
+    }
+  }
   if (d->n_steps != n - 1 || !d->steps) return fail(ctx, QF_ERR_PLAN, "a plan over n tensors needs exactly n-1 steps");
   std::vector<char> used(2 * n, 0);
   p->peak_bits = 0;
@@ -512,7 +543,8 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   const int S = (int)p->steps.size();
   for (int i = 0; i < S; ++i) {
     Node& nd = p->nodes[n + i];
-    const size_t bytes = align_up(sizeof(float2) << nd.labels.size());
+    const size_t G = (size_t)p->G;
+    const size_t bytes = align_up(G * (sizeof(float2) << nd.labels.size()));
     Step& st = p->steps[i];
     if (p->backward) {
       // every forward tensor is kept for the reverse sweep, next to its environment
@@ -524,8 +556,13 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     }
     if (nd.persistent) pers.push_back({bytes, 0, S, &nd.offset});
     else trans.push_back({bytes, i, (i == S - 1) ? S : nd.consumer, &nd.offset});
-    if (st.A.permute) trans.push_back({align_up(sizeof(float2) << st.A.nbits), i, i, &st.A.buf});
-    if (st.B.permute) trans.push_back({align_up(sizeof(float2) << st.B.nbits), i, i, &st.B.buf});
+    if (st.A.permute) trans.push_back({align_up(G * (sizeof(float2) << st.A.nbits)), i, i, &st.A.buf});
+    if (st.B.permute) trans.push_back({align_up(G * (sizeof(float2) << st.B.nbits)), i, i, &st.B.buf});
+  }
+  if (p->G > 1) {
+    pers.push_back({align_up(n * sizeof(LeafDesc)), 0, S, &p->off_leafdesc});
+    pers.push_back({align_up((size_t)p->G * n * sizeof(int64_t)), 0, S, &p->off_btable});
+    pers.push_back({align_up((size_t)p->G * sizeof(int32_t)), 0, S, &p->off_chainb});
   }
   if (p->backward) {
     size_t max_q = 0, max_c = 0, max_a = 0, max_b = 0;
@@ -578,6 +615,11 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
 
 void qf_plan_destroy(qf_plan* plan) {
   if (plan && plan->ctx && plan->ctx->last_built == plan) plan->ctx->last_built = nullptr;
+  if (plan && plan->gexec) {
+    hipStreamSynchronize(plan->ctx->stream);
+    hipGraphExecDestroy(plan->gexec);
+    hipGraphDestroy(plan->graph_obj);
+  }
   delete plan;
 }
 
@@ -659,6 +701,9 @@ static qf_status build_worldlines(qf_plan* p) {
   if (!p->wl_prog.empty())
     QF_HIP(c, hipMemcpyAsync(c->ws + p->off_prog, p->wl_prog.data(), p->wl_prog.size() * sizeof(WlInstr),
                              hipMemcpyHostToDevice, c->stream));
+  if (p->G > 1)
+    QF_HIP(c, hipMemcpyAsync(c->ws + p->off_leafdesc, p->leaf_desc.data(), p->leaf_desc.size() * sizeof(LeafDesc),
+                             hipMemcpyHostToDevice, c->stream));
   QF_HIP(c, launch_worldlines(c->stream, reinterpret_cast<const WlQubit*>(c->ws + p->off_wlq), p->n, p->max_nbond,
                               reinterpret_cast<const WlInstr*>(c->ws + p->off_prog),
                               reinterpret_cast<const float2*>(c->ws + p->off_gates), wsp(c, p->off_wl)));
@@ -714,17 +759,18 @@ static qf_status run_operand(qf_plan* p, const Operand& op, const uint8_t* bits_
 }
 
 // One GEMM of the plan's precision (FP16 takes the operands' max magnitudes first).
-static qf_status plan_gemm(qf_plan* p, int64_t M, int64_t N, int64_t K, const float2* A, const float2* B, float2* C) {
+static qf_status plan_gemm(qf_plan* p, int64_t M, int64_t N, int64_t K, const float2* A, const float2* B, float2* C,
+                           int64_t batch = 1) {
   qf_ctx* c = p->ctx;
   const uint32_t *amA = nullptr, *amB = nullptr;
   if (p->precision == QF_FP16) {
     uint32_t* slots = reinterpret_cast<uint32_t*>(c->ws);  // context scratch: 2 slots
-    QF_HIP(c, launch_amax(c->stream, A, M * K, slots));
-    QF_HIP(c, launch_amax(c->stream, B, N * K, slots + 1));
+    QF_HIP(c, launch_amax(c->stream, A, batch * M * K, slots));
+    QF_HIP(c, launch_amax(c->stream, B, batch * N * K, slots + 1));
     amA = slots;
     amB = slots + 1;
   }
-  QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, 1, 0, 0, 0, amA, amB));
+  QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, batch, M * K, N * K, M * N, amA, amB));
   return QF_OK;
 }
 
@@ -771,6 +817,126 @@ static qf_status prepare(qf_plan* p) {
   return QF_OK;
 }
 
+// ---- batched chains: every step runs G chains (bitstring x slice pairs) as one launch --------
+static qf_status run_operand_batched(qf_plan* p, const Operand& op, const float2** ptr) {
+  qf_ctx* c = p->ctx;
+  const Node& nd = p->nodes[op.node];
+  if (!op.permute) {
+    *ptr = wsp(c, nd.offset);
+    return QF_OK;
+  }
+  PermuteArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nbits = op.nbits;
+  for (int i = 0; i < op.nbits; ++i) a.perm[i] = op.perm[i];
+  a.scale = 1.0f;
+  a.batch = p->G;
+  a.dst_bstride = (int64_t)1 << op.nbits;
+  const float2* src;
+  if (nd.leaf) {
+    src = wsp(c, p->off_wl) + p->wl_qubits[nd.qubit].out_offset;
+    a.src_bstride = 0;
+    a.base_table = reinterpret_cast<const int64_t*>(c->ws + p->off_btable) + nd.qubit;
+    a.base_stride = p->n;
+  } else {
+    src = wsp(c, nd.offset);
+    a.src_bstride = (int64_t)1 << nd.labels.size();
+  }
+  float2* dst = wsp(c, op.buf);
+  QF_HIP(c, launch_permute(c->stream, src, dst, a));
+  *ptr = dst;
+  return QF_OK;
+}
+
+static qf_status enqueue_group(qf_plan* p, const uint8_t* bits_dev, int64_t s_begin, int64_t s_range,
+                               int64_t n_chains, double* out_dev, bool timed_ok) {
+  qf_ctx* c = p->ctx;
+  const int n = p->n, G = p->G, k = (int)p->open.size();
+  int64_t* chain0 = reinterpret_cast<int64_t*>(c->ws + 8);
+  int32_t* chain_b = reinterpret_cast<int32_t*>(c->ws + p->off_chainb);
+  QF_HIP(c, launch_chain_setup(c->stream, chain0, G, n, reinterpret_cast<const LeafDesc*>(c->ws + p->off_leafdesc),
+                               bits_dev, n, s_begin, s_range, n_chains,
+                               reinterpret_cast<int64_t*>(c->ws + p->off_btable), chain_b));
+  for (size_t i = 0; i < p->steps.size(); ++i) {
+    const Step& st = p->steps[i];
+    const float2 *A, *B;
+    qf_status e = run_operand_batched(p, st.A, &A);
+    if (e != QF_OK) return e;
+    e = run_operand_batched(p, st.B, &B);
+    if (e != QF_OK) return e;
+    float2* C = wsp(c, p->nodes[n + i].offset);
+    const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+    const bool timed = timed_ok && c->profile && st.flops == p->max_step_flops;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+      e0 = take_event(c);
+      e1 = take_event(c);
+      if (e0 && e1) QF_HIP(c, hipEventRecord(e0, c->stream));
+    }
+    e = plan_gemm(p, M, N, K, A, B, C, G);
+    if (e != QF_OK) return e;
+    if (timed && e0 && e1) {
+      QF_HIP(c, hipEventRecord(e1, c->stream));
+      c->ev_used.push_back({e0, e1});
+      c->prof_flops += st.flops * G;
+      ++c->prof_launches;
+    }
+  }
+  QF_HIP(c, launch_slice_accumulate_batched(c->stream, wsp(c, p->nodes.back().offset), k, p->root_pos.data(), G,
+                                            chain_b, reinterpret_cast<double2*>(out_dev)));
+  QF_HIP(c, launch_chain_counter(c->stream, chain0, G, 1));
+  return QF_OK;
+}
+
+static qf_status amplitudes_batched(qf_plan* p, int n_batch, const uint8_t* bits_dev, int64_t s_begin, int64_t s_end,
+                                    double* out_dev) {
+  qf_ctx* c = p->ctx;
+  const int64_t s_range = s_end - s_begin;
+  const int64_t n_chains = (int64_t)n_batch * s_range;
+  const int64_t groups = (n_chains + p->G - 1) / p->G;
+  int64_t* chain0 = reinterpret_cast<int64_t*>(c->ws + 8);
+  QF_HIP(c, launch_chain_counter(c->stream, chain0, 0, 0));
+  if (!(p->graph && c->stream)) {
+    for (int64_t g = 0; g < groups; ++g) {
+      qf_status e = enqueue_group(p, bits_dev, s_begin, s_range, n_chains, out_dev, true);
+      if (e != QF_OK) return e;
+    }
+    return QF_OK;
+  }
+  const std::vector<int64_t> key = {(int64_t)(uintptr_t)c->ws, (int64_t)(uintptr_t)bits_dev,
+                                    (int64_t)(uintptr_t)out_dev, n_batch, s_begin, s_end,
+                                    (int64_t)(uintptr_t)c->stream};
+  if (!p->gexec || key != p->graph_key) {
+    if (p->gexec) {
+      QF_HIP(c, hipStreamSynchronize(c->stream));
+      hipGraphExecDestroy(p->gexec);
+      hipGraphDestroy(p->graph_obj);
+      p->gexec = nullptr;
+      p->graph_obj = nullptr;
+    }
+    QF_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    qf_status e = enqueue_group(p, bits_dev, s_begin, s_range, n_chains, out_dev, false);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(c->stream, &graph);
+    if (e != QF_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return e;
+    }
+    if (ce != hipSuccess) return hip_fail(c, ce, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ce != hipSuccess) {
+      hipGraphDestroy(graph);
+      return hip_fail(c, ce, "hipGraphInstantiate");
+    }
+    p->gexec = exec;
+    p->graph_obj = graph;
+    p->graph_key = key;
+  }
+  for (int64_t g = 0; g < groups; ++g) QF_HIP(c, hipGraphLaunch(p->gexec, c->stream));
+  return QF_OK;
+}
+
 extern "C" qf_status qf_amplitudes(qf_plan* p, int n_batch, const uint8_t* bits_dev, int64_t s_begin, int64_t s_end,
                                    double* out_dev) {
   if (!p) return QF_ERR_ARG;
@@ -783,6 +949,7 @@ extern "C" qf_status qf_amplitudes(qf_plan* p, int n_batch, const uint8_t* bits_
   if (n_batch == 0 || s_begin == s_end) return QF_OK;
   qf_status e = prepare(p);
   if (e != QF_OK) return e;
+  if (p->G > 1) return amplitudes_batched(p, n_batch, bits_dev, s_begin, s_end, out_dev);
   int64_t fault_after = -1;
   if (const char* f = std::getenv("QFMI_FAULT_AFTER_SLICES")) fault_after = std::atoll(f);
   const int n = p->n;

@@ -240,4 +240,76 @@ hipError_t launch_zero(hipStream_t st, void* p, size_t bytes) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------------
+// Batched chains (bitstring x slice): per-chain leaf offsets and the ordered FP64 slice sum.
+__global__ void __launch_bounds__(256)
+chain_setup_kernel(const int64_t* __restrict__ chain0, int G, int n_leaves, const LeafDesc* __restrict__ leaves,
+                   const uint8_t* __restrict__ bits, int n_qubits, int64_t s_begin, int64_t s_range,
+                   int64_t n_chains, int64_t* __restrict__ base_table, int32_t* __restrict__ chain_b) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= G * n_leaves) return;
+  const int g = t / n_leaves, l = t - g * n_leaves;
+  const int64_t c = *chain0 + g;
+  int64_t base = 0;
+  int32_t b = -1;
+  if (c < n_chains) {
+    b = (int32_t)(c / s_range);
+    const int64_t s = s_begin + (c - (int64_t)b * s_range);
+    const LeafDesc& d = leaves[l];
+    for (int i = 0; i < d.n_cut; ++i) base |= ((s >> d.shift[i]) & 1) << d.pos[i];
+    if (d.xpos >= 0) base |= (int64_t)(bits[(int64_t)b * n_qubits + d.qubit] & 1) << d.xpos;
+  }
+  base_table[t] = base;
+  if (l == 0) chain_b[g] = b;
+}
+
+hipError_t launch_chain_setup(hipStream_t st, const int64_t* chain0, int G, int n_leaves, const LeafDesc* leaves,
+                              const uint8_t* bits, int n_qubits, int64_t s_begin, int64_t s_range, int64_t n_chains,
+                              int64_t* base_table, int32_t* chain_b) {
+  const int total = G * n_leaves;
+  hipLaunchKernelGGL(chain_setup_kernel, dim3((total + 255) / 256), dim3(256), 0, st, chain0, G, n_leaves, leaves,
+                     bits, n_qubits, s_begin, s_range, n_chains, base_table, chain_b);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256)
+slice_accumulate_batched_kernel(const float2* __restrict__ root, AccArgs a, int G, const int32_t* __restrict__ chain_b,
+                                double2* __restrict__ out) {
+  const int64_t n = (int64_t)1 << a.k;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    int64_t src = 0;
+    for (int t = 0; t < a.k; ++t) src |= ((j >> t) & 1) << a.pos[t];
+    for (int g = 0; g < G; ++g) {
+      const int32_t b = chain_b[g];
+      if (b < 0) continue;
+      const float2 v = root[(int64_t)g * n + src];
+      double2 o = out[((int64_t)b << a.k) + j];
+      o.x += (double)v.x;
+      o.y += (double)v.y;
+      out[((int64_t)b << a.k) + j] = o;
+    }
+  }
+}
+
+hipError_t launch_slice_accumulate_batched(hipStream_t st, const float2* root, int k, const int* pos, int G,
+                                           const int32_t* chain_b, double2* out) {
+  AccArgs a;
+  a.k = k;
+  for (int t = 0; t < 32; ++t) a.pos[t] = t < k ? pos[t] : 0;
+  const int64_t n = (int64_t)1 << k;
+  unsigned blocks = (unsigned)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(slice_accumulate_batched_kernel, dim3(blocks), dim3(256), 0, st, root, a, G, chain_b, out);
+  return hipGetLastError();
+}
+
+__global__ void chain_counter_kernel(int64_t* chain0, int64_t value, int add) {
+  if (threadIdx.x == 0) *chain0 = add ? *chain0 + value : value;
+}
+
+hipError_t launch_chain_counter(hipStream_t st, int64_t* chain0, int64_t value, int add) {
+  hipLaunchKernelGGL(chain_counter_kernel, dim3(1), dim3(64), 0, st, chain0, value, add);
+  return hipGetLastError();
+}
+
 } // namespace qf

@@ -1,0 +1,159 @@
+"""Batched chains (G bitstring x slice pairs per launch) and their hipGraph replay: identical
+to the one-chain-at-a-time path, and correct against the oracle and closed forms, including
+the 70-qubit (8x9 minus two corners, 1+24+1) workload's shapes."""
+import numpy as np
+import pytest
+
+from oracle import sv
+from oracle.metrics import rel_err
+from workloads.bitstrings import random_bitstrings
+from workloads.circuits import generate, identity_cz
+from workloads.plans import region_plan, plan_8x9, C5_REMOVED
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1905_00444_amd import Context
+    assert torch.cuda.is_available()
+    return Context(0)
+
+
+@pytest.fixture(scope="module")
+def gctx():
+    """A context on a non-default stream (graph capture needs one)."""
+    import torch
+    from paper_1905_00444_amd import Context
+    return Context(0, stream=torch.cuda.Stream())
+
+
+def _setup_4x5():
+    c = generate(4, 5, 32, 2)
+    qid = c.qubit_of()
+    cuts = [[qid[(1, 3)], qid[(2, 3)], 0, 2], [qid[(3, 1)], qid[(3, 2)], 1, 2]]
+    plan, _ = region_plan(c, 2, 2, cuts, [(3, 4), (2, 4)])
+    return c, plan
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("G", [2, 8])
+def test_batched_equals_sequential_bitwise(ctx, precision, G):
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    _say(f"batched G={G} {precision}")
+    c, plan = _setup_4x5()
+    bits = random_bitstrings(3, 20, 5)  # 3 x 16 = 48 chains: 48 / 8 leaves no tail, 48 / 32 would
+    circ = Circuit(ctx, c.to_text())
+    seq = Plan(ctx, circ, plan, precision, hoist=False).amplitudes(bits)
+    bat = Plan(ctx, circ, plan, precision, batch=G).amplitudes(bits)
+    torch.cuda.synchronize()
+    assert np.array_equal(seq.cpu().numpy(), bat.cpu().numpy())
+
+
+def test_batched_tail_and_slice_subrange(ctx):
+    """Chains that do not fill the last group are masked; slice sub-ranges compose."""
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    _say("batched tail")
+    c, plan = _setup_4x5()
+    bits = random_bitstrings(3, 20, 6)
+    circ = Circuit(ctx, c.to_text())
+    seq = Plan(ctx, circ, plan, "fp32", hoist=False).amplitudes(bits, 3, 10)  # 21 chains
+    bat = Plan(ctx, circ, plan, "fp32", batch=8).amplitudes(bits, 3, 10)
+    torch.cuda.synchronize()
+    assert np.array_equal(seq.cpu().numpy(), bat.cpu().numpy())
+    ref = sv.open_amplitudes(c.to_text(), bits, plan["open"])
+    full = Plan(ctx, circ, plan, "fp32", batch=8).amplitudes(bits)
+    torch.cuda.synchronize()
+    assert rel_err(full.cpu().numpy(), ref) <= 1e-5
+
+
+def test_graph_replays_match_eager(gctx):
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    _say("graph replay")
+    c, plan = _setup_4x5()
+    bits = random_bitstrings(4, 20, 7)
+    circ = Circuit(gctx, c.to_text())
+    eager = Plan(gctx, circ, plan, "bf16x3", batch=4)
+    graph = Plan(gctx, circ, plan, "bf16x3", batch=4, graph=True)
+    ref = eager.amplitudes(bits)
+    gctx.synchronize()
+    ref = ref.cpu().numpy()
+    bits_t = torch.from_numpy(bits).to(gctx.device)
+    with torch.cuda.stream(gctx.stream):
+        out = torch.zeros((4, 4), dtype=torch.complex128, device=gctx.device)
+    for rep in range(4):
+        with torch.cuda.stream(gctx.stream):
+            out.zero_()
+        graph.amplitudes(bits_t, out=out)  # same pointers every time: the captured graph is replayed
+        gctx.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), rep
+        # eager work between replays
+        eager.amplitudes(bits)
+        gctx.synchronize()
+
+
+def _product_slice(circ, plan, bits_row, s):
+    from oracle import gates
+    total = sum(x[3] for x in plan["cuts"])
+    fixed = {}
+    off = total
+    for q0, q1, lo, nb in plan["cuts"]:
+        off -= nb
+        v = (s >> off) & ((1 << nb) - 1)
+        for i in range(nb):
+            fixed[(q0, q1, lo + i)] = (v >> (nb - 1 - i)) & 1
+    vecs = [np.array([1, 0], dtype=np.complex128) for _ in range(circ.n_qubits)]
+    seen = {}
+    for op in circ.ops:
+        if len(op.qubits) == 1:
+            vecs[op.qubits[0]] = gates.one_qubit(op.name) @ vecs[op.qubits[0]]
+        else:
+            j = seen.get(op.qubits, 0)
+            seen[op.qubits] = j + 1
+            if op.qubits + (j,) in fixed:
+                q0 = op.qubits[0]
+                vecs[q0] = vecs[q0] * (np.arange(2) == fixed[op.qubits + (j,)])
+    return np.prod([vecs[q][bits_row[q]] for q in range(circ.n_qubits)])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_70_qubit_product_circuit_batched_graph(gctx, precision):
+    """8x9 minus two corners, (1+24+1), every CZ -> identity: each chain has a closed form.
+    16 bitstrings x slices 0..7 run as 128 chains, 32 per launch, through the captured graph."""
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    _say(f"70 qubits product circuit {precision}")
+    base = generate(8, 9, 24, 0, C5_REMOVED)
+    plan, _ = plan_8x9(base)
+    c = identity_cz(base)
+    bits = random_bitstrings(16, 70, 1)
+    p = Plan(gctx, Circuit(gctx, c.to_text()), plan, precision, batch=32, graph=True)
+    got = p.amplitudes(bits, 0, 8)
+    gctx.synchronize()
+    ref = np.array([sum(_product_slice(c, plan, bits[b], s) for s in range(8)) for b in range(16)])
+    assert rel_err(got.cpu().numpy()[:, 0], ref) <= (1e-5 if precision == "fp32" else 1e-4)
+
+
+def test_70_qubit_random_circuit_batched_vs_oracle_one_chain(gctx):
+    """One chain (bitstring 0, slice 5) of the random 70-qubit circuit against the FP64
+    tensor-network oracle, through the batched graph path."""
+    import torch
+    from oracle import tn
+    from paper_1905_00444_amd import Circuit, Plan
+    _say("70 qubits random, one chain vs oracle")
+    c = generate(8, 9, 24, 0, C5_REMOVED)
+    plan, _ = plan_8x9(c)
+    bits = random_bitstrings(1, 70, 1)
+    p = Plan(gctx, Circuit(gctx, c.to_text()), plan, "fp32", batch=2, graph=True)
+    got = p.amplitudes(bits, 5, 6)
+    gctx.synchronize()
+    ref = tn.amplitudes(c.to_text(), bits, plan, slices=[5])
+    assert rel_err(got.cpu().numpy(), ref) <= 1e-5

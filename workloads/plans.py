@@ -179,3 +179,27 @@ def plan_7x7(circ: Circuit, depth: int) -> Tuple[dict, PlanBuilder]:
     cut_d = [min(qid[(6, 2)], qid[(6, 3)]), max(qid[(6, 2)], qid[(6, 3)]), 0, nb]
     cuts = [cut_d] if depth <= 32 else [cut_b, cut_d]
     return region_plan(circ, 3, 3, cuts, C4_OPEN_SITES)
+
+
+# 8x9 grid with corners (0,0) and (7,8) removed: 70 qubits.
+C5_REMOVED = ((0, 0), (7, 8))
+
+
+def plan_8x9(circ: Circuit, depth: int = 24) -> Tuple[dict, PlanBuilder]:
+    """Two halves (columns 0-4 and 5-8) grown greedily from their removed corners and joined in
+    one last contraction; 8 cut bits on the boundary between them -> 256 slices: the whole
+    bonds (0,4)-(0,5) and (1,4)-(1,5) and the two leading bits of (2,4)-(2,5) (a partial cut,
+    paper Sec. III-A: slice sizes may be chosen adaptively).  Peak tensor 2^27."""
+    qid = circ.qubit_of()
+    nb = depth // 8
+    cuts = []
+    for r, bits in ((0, nb), (1, nb), (2, 2)):
+        a, b = qid[(r, 4)], qid[(r, 5)]
+        cuts.append([min(a, b), max(a, b), 0, bits])
+    pb = PlanBuilder(circ, cuts, [])
+    left = [(r, c) for c in range(5) for r in range(circ.rows) if (r, c) in qid]
+    right = [(r, c) for c in range(circ.cols - 1, 4, -1) for r in range(circ.rows) if (r, c) in qid]
+    L = pb.greedy_region(left, (1, 0))
+    R = pb.greedy_region(right, (6, 8))
+    pb.contract(L, R)
+    return pb.plan(), pb
