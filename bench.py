@@ -30,10 +30,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--slices", type=int, default=6, help="slices per step (fidelity slices/1024)")
     ap.add_argument("--fp32-steps", type=int, default=1)
-    ap.add_argument("--cpu-sample-steps", type=int, default=5,
-                    help="plan steps of the oracle timed for the CPU baseline")
+    ap.add_argument("--cpu-reps", type=int, default=10, help="prefixes in the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-subcheck", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="launch one plain 1 GiB device copy first (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -60,18 +61,37 @@ def sub_check(ctx):
     return out
 
 
-def cpu_baseline(circ, plan, pb, bits_row, flops_per_step, n_amp, n_steps):
-    """Time the FP64 oracle on the first `n_steps` contractions of slice 0 (a bounded sample
-    of the same workload) and scale its flop rate to amplitudes/s of one bench step."""
+def cpu_sample_steps(plan, pb, max_bits=25):
+    """Plan steps whose operands and result all stay at or below 2^max_bits elements and whose
+    inputs are leaves or other such steps (a bounded, representative part of the workload)."""
+    n = pb.n
+    ok = set(range(n))
+    sel = []
+    for i, ((a, b), vc) in enumerate(zip(plan["steps"], pb.sizes())):
+        va, vb = pb.bits_of(pb.members[a]), pb.bits_of(pb.members[b])
+        if a in ok and b in ok and max(va, vb, vc) <= max_bits:
+            ok.add(n + i)
+            sel.append(i)
+    return sel
+
+
+def cpu_baseline(circ, plan, pb, bits, flops_per_step, n_amp, reps):
+    """Time the FP64 oracle on a bounded sample of the same workload (the plan's steps whose
+    tensors stay at or below 2^25 elements, slice 0, `reps` prefixes) and scale its flop rate
+    to amplitudes/s of one bench step."""
     from oracle import tn
     text = circ.to_text()
-    t0 = time.perf_counter()
-    tn.partial_contract(text, bits_row, plan, 0, n_steps)
-    dt = time.perf_counter() - t0
+    sel = cpu_sample_steps(plan, pb)
     fl = 0.0
-    for (a, b), vc in list(zip(plan["steps"], pb.sizes()))[:n_steps]:
+    for i in sel:
+        (a, b), vc = plan["steps"][i], pb.sizes()[i]
         va, vb = pb.bits_of(pb.members[a]), pb.bits_of(pb.members[b])
         fl += 8 * 2.0 ** ((va + vb + vc) / 2)
+    t0 = time.perf_counter()
+    for r in range(reps):
+        tn.partial_contract(text, bits[r], plan, 0, subset=sel)
+    dt = time.perf_counter() - t0
+    fl *= reps
     rate = fl / dt
     try:
         from threadpoolctl import threadpool_info
@@ -79,9 +99,10 @@ def cpu_baseline(circ, plan, pb, bits_row, flops_per_step, n_amp, n_steps):
     except Exception:
         cores = os.cpu_count()
     return {"value": n_amp * rate / flops_per_step, "unit": "amplitudes/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 numpy oracle: first {n_steps} contractions of slice 0 of the 7x7 (1+40+1) plan "
-                      f"({fl:.3e} flop in {dt:.1f} s = {rate / 1e9:.1f} GFLOP/s), scaled by flops to one step "
-                      f"({flops_per_step:.3e} flop, {n_amp} amplitudes)",
+            "sample": f"FP64 numpy oracle on {len(sel)} of the {len(plan['steps'])} contractions of the 7x7 (1+40+1) "
+                      f"plan (those with tensors <= 2^25 elements), slice 0, {reps} prefixes: {fl:.3e} flop in "
+                      f"{dt:.1f} s = {rate / 1e9:.1f} GFLOP/s, scaled by flops to one step ({flops_per_step:.3e} "
+                      f"flop, {n_amp} amplitudes)",
             "fp64_gflops": rate / 1e9}
 
 
@@ -110,11 +131,20 @@ def main():
     n_amp = 2 ** info["n_open"]
     ctx.ensure_workspace(info["workspace_bytes"])
 
+    if args.calib_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
     def run(prec, i):
         return plans[prec].amplitudes(bits[i % len(bits):i % len(bits) + 1], 0, S)
 
     results = {}
     for prec, steps in (("bf16x3", args.steps), ("fp32", args.fp32_steps)):
+        if steps <= 0:
+            continue
         for w in range(args.warmup):
             run(prec, w)
             torch.cuda.synchronize()
@@ -137,16 +167,21 @@ def main():
                          "gemm_ms": gms, "gemm_launches": glaunch, "gemm_flops": gflops}
         print(f"bench: {prec} {steps} steps in {dt:.2f} s", file=sys.stderr, flush=True)
 
-    bf, fp = results["bf16x3"], results["fp32"]
+    bf = results["bf16x3"]
+    fp = results.get("fp32")
     ms_step = bf["s"] / bf["steps"] * 1e3
     value = n_amp * bf["steps"] / bf["s"]
-    fp_value = n_amp * fp["steps"] / fp["s"]
     tflops = flops_step * bf["steps"] / bf["s"] / 1e12
-    fp_tflops = flops_step * fp["steps"] / fp["s"] / 1e12
+    fp_value = n_amp * fp["steps"] / fp["s"] if fp else None
+    fp_tflops = flops_step * fp["steps"] / fp["s"] / 1e12 if fp else None
     # self-consistency of the two precisions on the same prefixes
-    k = min(len(fp["amps"]), len(bf["amps"]))
-    from numpy.linalg import norm
-    bf_vs_fp = float(norm(bf["amps"][:k] - fp["amps"][:k]) / norm(fp["amps"][:k]))
+    bf_vs_fp = None
+    if fp:
+        from numpy.linalg import norm
+        k = min(len(fp["amps"]), len(bf["amps"]))
+        den = norm(fp["amps"][:k])
+        bf_vs_fp = float(norm(bf["amps"][:k] - fp["amps"][:k]) / den) if den > 0 else None
+        rec_norms = {"bf16x3": float(norm(bf["amps"][:k])), "fp32": float(den)}
     gemm_avg_ms = bf["gemm_ms"] / max(1, bf["gemm_launches"])
     per_launch = bf["gemm_flops"] / max(1, bf["gemm_launches"])
     achieved = per_launch / (gemm_avg_ms * 1e-3) / 1e12 if gemm_avg_ms > 0 else 0.0
@@ -161,9 +196,9 @@ def main():
                                f"per prefix), {S} slices per step", "global_batch": n_amp, "slices_per_step": S,
                    "parallelism": "single GPU"},
         "complex_tflops": tflops,
-        "fp32": {"value": fp_value, "complex_tflops": fp_tflops, "steps": fp["steps"],
-                 "ms_per_step": fp["s"] / fp["steps"] * 1e3},
-        "speedup_bf16x3_vs_fp32": value / fp_value,
+        "fp32": ({"value": fp_value, "complex_tflops": fp_tflops, "steps": fp["steps"],
+                  "ms_per_step": fp["s"] / fp["steps"] * 1e3} if fp else None),
+        "speedup_bf16x3_vs_fp32": value / fp_value if fp else None,
         "rel_err_bf16x3_vs_fp32_same_prefixes": bf_vs_fp,
         "flops_per_step": flops_step,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
@@ -173,12 +208,14 @@ def main():
                                   "achieved counts algorithmic complex flops 8*M*N*K",
                      "launches": bf["gemm_launches"], "avg_ms": gemm_avg_ms},
     }
+    if fp:
+        rec["amplitude_norms_same_prefixes"] = rec_norms
     if not args.no_subcheck:
         print("bench: 4x4 (1+40+1) sub-check vs FP64 state vector", file=sys.stderr, flush=True)
         rec["rel_err_vs_fp64_4x4_d40"] = sub_check(ctx)
     if not args.no_cpu:
         print("bench: CPU oracle sample", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(circ, plan, pb, bits[0], flops_step, n_amp, args.cpu_sample_steps)
+        rec["cpu_baseline"] = cpu_baseline(circ, plan, pb, bits, flops_step, n_amp, args.cpu_reps)
     print(json.dumps(rec), flush=True)
     return 0
 

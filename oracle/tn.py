@@ -145,23 +145,25 @@ def amplitudes(circ, bits: np.ndarray, plan: Optional[dict] = None, slices=None)
     return out
 
 
-def partial_contract(circ, bits_row: np.ndarray, plan: dict, s: int, n_steps: int):
-    """Run only the first n_steps contractions of slice s (used to time a bounded sample of a
-    large workload); returns the last intermediate and its labels."""
+def partial_contract(circ, bits_row: np.ndarray, plan: dict, s: int, n_steps: int = None, subset=None):
+    """Run only some contractions of slice s (used to time a bounded sample of a large
+    workload): the first n_steps, or the step indices in `subset` (ascending; each step's
+    inputs must be leaves or results of earlier listed steps).  Returns the last result."""
     if isinstance(circ, str):
         circ = read_circuit(circ)
     n = circ.n
     tens, labels = world_lines(circ)
     open_q = list(plan.get("open", []))
     cutv = _cut_values(plan.get("cuts", []), s)
-    nodes = []
+    nodes = {}
     for q in range(n):
         bit = None if q in open_q else int(bits_row[q])
-        nodes.append(_leaf(tens[q], labels[q], q, bit, cutv))
+        nodes[q] = _leaf(tens[q], labels[q], q, bit, cutv)
+    idx = list(range(n_steps)) if subset is None else list(subset)
     last = None
-    for a, b in plan["steps"][:n_steps]:
-        (ta, la), (tb, lb) = nodes[a], nodes[b]
+    for i in idx:
+        a, b = plan["steps"][i]
+        (ta, la), (tb, lb) = nodes.pop(a), nodes.pop(b)
         last = _contract(ta, la, tb, lb)
-        nodes.append(last)
-        nodes[a] = nodes[b] = None
+        nodes[n + i] = last
     return last
