@@ -183,6 +183,21 @@ qf_status qf_cgemm(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, 
                    const void* B, void* C, int64_t batch, int64_t stride_a, int64_t stride_b,
                    int64_t stride_c);
 
+/* Split-BF16 operand (the conversion the split-BF16 GEMM consumes, Sec. III-E's "T" step
+ * writes it directly when it precedes such a GEMM): for j < 2^nbits complex64 src[j] = x,
+ * writes hi = bf16(x) (round to nearest even, re and im) into 32-bit word j of dst and
+ * lo = bf16(x - hi) into word 2^nbits + j: dst holds 2^(nbits+1) words = 8 * 2^nbits bytes. */
+qf_status qf_split_bf16(qf_ctx* ctx, const void* src, void* dst, int nbits);
+
+/* Split-BF16 complex GEMM on operands produced by qf_split_bf16 (A of M x K, B of N x K
+ * elements, row-major, K contiguous): C[m][n] = sum_k A[m][k] B[n][k] as
+ * hi*hi + hi*lo + lo*hi with FP32 accumulation, C complex64 row-major.  Needs powers of two
+ * with M >= 256, N >= 128, K >= 16 (QF_ERR_UNSUPPORTED otherwise). */
+qf_status qf_cgemm_presplit(qf_ctx* ctx, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
+                            void* C);
+qf_status qf_time_cgemm_presplit(qf_ctx* ctx, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
+                                 void* C, int reps, float* ms);
+
 /* Time one launch configuration of qf_cgemm / qf_permute with HIP events on the context's
  * stream: runs `reps` launches and returns the average milliseconds per launch in *ms.
  * Synchronises the stream. */

@@ -254,6 +254,35 @@ def cgemm(ctx: Context, A, B, precision: str = "fp32", out=None):
     return out
 
 
+def split_bf16(ctx: Context, x, out=None):
+    """Split-BF16 form of a complex64 tensor of 2^b elements: hi plane then lo plane (uint32 words)."""
+    torch = _torch()
+    n = x.numel()
+    b = n.bit_length() - 1
+    assert n == 1 << b and x.dtype == torch.complex64
+    if out is None:
+        out = torch.empty(2 * n, dtype=torch.int32, device=x.device)
+    check(ctx.lib.qf_split_bf16(ctx.h, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), b), ctx.h)
+    return out
+
+
+def cgemm_presplit(ctx: Context, As, Bs, M: int, N: int, K: int, out=None):
+    """C = A B^T from split operands (see split_bf16)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((M, N), dtype=torch.complex64, device=As.device)
+    check(ctx.lib.qf_cgemm_presplit(ctx.h, M, N, K, C.c_void_p(As.data_ptr()), C.c_void_p(Bs.data_ptr()),
+                                    C.c_void_p(out.data_ptr())), ctx.h)
+    return out
+
+
+def time_cgemm_presplit(ctx: Context, As, Bs, C_out, M: int, N: int, K: int, reps: int = 5) -> float:
+    ms = C.c_float()
+    check(ctx.lib.qf_time_cgemm_presplit(ctx.h, M, N, K, C.c_void_p(As.data_ptr()), C.c_void_p(Bs.data_ptr()),
+                                         C.c_void_p(C_out.data_ptr()), reps, C.byref(ms)), ctx.h)
+    return ms.value
+
+
 def time_cgemm(ctx: Context, A, B, C_out, precision: str, reps: int = 5) -> float:
     M, K = A.shape
     N = B.shape[0]

@@ -116,9 +116,15 @@ __device__ __forceinline__ void load_tile(float4 (&r)[ROWS * 16 / kThreads], con
 }
 
 // B operand for real column (n, q): q = 0 -> (br, -bi), q = 1 -> (bi, br), per packed complex.
-__device__ __forceinline__ uint32_t bexpand16(uint32_t w, int q) {
-  return q ? ((w >> 16) | (w << 16)) : (w ^ 0x80000000u);
-}
+// Branch-free with per-lane constants: rot = 16 q (rotate the two halves), flip = q ? 0 : sign
+// bit of the upper half.
+struct BExpand {
+  uint32_t rot, flip;
+  __device__ explicit BExpand(int q) : rot(q ? 16u : 0u), flip(q ? 0u : 0x80000000u) {}
+  __device__ __forceinline__ uint32_t operator()(uint32_t w) const {
+    return __builtin_amdgcn_alignbit(w, w, rot) ^ flip;
+  }
+};
 
 template <int PREC, int WTM, int WTN>
 __global__ void __launch_bounds__(kThreads)
@@ -204,7 +210,7 @@ cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
       }
     } else {
       // 2 chunks of 16 complex k; lane group lg holds complex k 4*lg .. 4*lg+3 (8 real k)
-      const int q = l16 & 1;
+      const BExpand bx(l16 & 1);
 #pragma unroll
       for (int c = 0; c < kBK / 16; ++c) {
         u4 ah[WTM], al[WTM];
@@ -219,11 +225,11 @@ cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
           const char* p = ldsB + (wc + 8 * j + (l16 >> 1)) * LB::row_bytes + (16 * c + 4 * lg) * 4;
           u4 bh = *reinterpret_cast<const u4*>(p);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) bh[e] = bexpand16(bh[e], q);
+          for (int e = 0; e < 4; ++e) bh[e] = bx(bh[e]);
           if constexpr (PREC == P_BF16X3) {
             u4 bl = *reinterpret_cast<const u4*>(p + LB::plane_bytes);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) bl[e] = bexpand16(bl[e], q);
+            for (int e = 0; e < 4; ++e) bl[e] = bx(bl[e]);
             const bf8 vbh = __builtin_bit_cast(bf8, bh), vbl = __builtin_bit_cast(bf8, bl);
 #pragma unroll
             for (int i = 0; i < WTM; ++i)
@@ -366,6 +372,7 @@ cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const fl
   const int wr = (wave >> 1) * 64;  // first row of the wave
   const int wc = (wave & 1) * 64;   // first complex column of the wave
   const int l16 = lane & 15, lg = lane >> 4, q = l16 & 1;
+  const BExpand bx(q);
 
   float scale_a = 1.f, scale_b = 1.f, unscale = 1.f;
   if constexpr (PREC == P_FP16) {
@@ -403,11 +410,11 @@ cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const fl
       const char* p = LB + (wc + 8 * j + (l16 >> 1)) * kV2Row + lg * 16;
       u4 bh = *reinterpret_cast<const u4*>(p);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) bh[e] = bexpand16(bh[e], q);
+      for (int e = 0; e < 4; ++e) bh[e] = bx(bh[e]);
       if constexpr (PREC == P_BF16X3) {
         u4 bl = *reinterpret_cast<const u4*>(p + kV2PlaneB);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) bl[e] = bexpand16(bl[e], q);
+        for (int e = 0; e < 4; ++e) bl[e] = bx(bl[e]);
         const bf8 vbh = __builtin_bit_cast(bf8, bh), vbl = __builtin_bit_cast(bf8, bl);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -473,6 +480,162 @@ cgemm_simt(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
     }
     C[m * N + n] = make_float2(cr, ci);
   }
+}
+
+// Large shapes, split-BF16 on operands already split in HBM (hi and lo planes of bfloat16
+// complex numbers, [rows][K] each, written by the permute that precedes the GEMM).  Same
+// tiling as the kernel above (256 x 128 complex block, 8 waves of 4 x 8 MFMA tiles, K-tiles of
+// 16 complex) but the operands travel HBM -> LDS directly (global_load_lds_dwordx4: each lane
+// moves 16 bytes, one instruction fills 1 KiB = 16 rows x 64 bytes of one plane), through a
+// ring of 3 LDS stages: while tile kt is multiplied, tiles kt+1 and kt+2 are in flight.  Each
+// wave waits only for its own loads of tile kt (vmcnt), then one barrier makes every wave's
+// loads visible.  Within each 16-row group the four 16-byte chunks of a row are stored in the
+// order c ^ ((row >> 2) & 3), so the MFMA operand reads of 16 consecutive rows hit 16 distinct
+// bank groups.
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(1))) void* gbl_ptr_t;
+
+constexpr int kV3Threads = 512;
+constexpr int kV3BM = 256, kV3BN = 128, kV3BK = 16;
+constexpr int kV3PlaneA = kV3BM * 64;                       // 16 KiB
+constexpr int kV3PlaneB = kV3BN * 64;                       // 8 KiB
+constexpr int kV3Stage = 2 * kV3PlaneA + 2 * kV3PlaneB;     // 48 KiB
+constexpr int kV3Stages = 3;
+constexpr int kV3LoadsPerWave = (kV3Stage / 1024) / (kV3Threads / 64);  // 6
+
+__device__ __forceinline__ void v3_issue(char* stage, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
+                                         const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl,
+                                         int64_t K, int64_t k0, int wave, int lane) {
+  const int r = lane >> 2, pos = lane & 3;
+  const int c = pos ^ ((r >> 2) & 3);
+#pragma unroll
+  for (int t = 0; t < kV3LoadsPerWave; ++t) {
+    const int q = wave + 8 * t;  // 1 KiB chunk of the stage: 0..31 A (hi 0..15, lo 16..31), 32..47 B
+    const uint32_t* src;
+    int off;
+    if (q < 32) {
+      const int plane = q >> 4, r0 = (q & 15) * 16;
+      src = (plane ? Al : Ah) + (int64_t)(r0 + r) * K + k0 + 4 * c;
+      off = plane * kV3PlaneA + r0 * 64;
+    } else {
+      const int qq = q - 32, plane = qq >> 3, r0 = (qq & 7) * 16;
+      src = (plane ? Bl : Bh) + (int64_t)(r0 + r) * K + k0 + 4 * c;
+      off = 2 * kV3PlaneA + plane * kV3PlaneB + r0 * 64;
+    }
+    __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)(stage + off), 16, 0, 0);
+  }
+}
+
+__global__ void __launch_bounds__(kV3Threads)
+cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
+                  const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl, float2* __restrict__ C,
+                  int64_t sa, int64_t sb, int64_t sc) {
+  __shared__ __attribute__((aligned(1024))) char lds[kV3Stages * kV3Stage];
+
+  const int64_t tiles_m = M / kV3BM, tiles_n = N / kV3BN;
+  const int64_t ntiles = tiles_m * tiles_n;
+  int64_t bid = blockIdx.x;
+  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  const int64_t group = 8;
+  const int64_t per_group = group * tiles_n;
+  const int64_t gidx = bid / per_group;
+  const int64_t first_m = gidx * group;
+  const int64_t gsize = (tiles_m - first_m) < group ? (tiles_m - first_m) : group;
+  const int64_t tm = first_m + (bid % per_group) % gsize;
+  const int64_t tn = (bid % per_group) / gsize;
+
+  const int64_t batch = blockIdx.z;
+  Ah += batch * sa + tm * kV3BM * K;
+  Al += batch * sa + tm * kV3BM * K;
+  Bh += batch * sb + tn * kV3BN * K;
+  Bl += batch * sb + tn * kV3BN * K;
+  C += batch * sc;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 64;
+  const int wc = (wave & 1) * 64;
+  const int l16 = lane & 15, lg = lane >> 4, q = l16 & 1;
+  const BExpand bx(q);
+  // swizzled 16-byte chunk of this lane's operand reads
+  const int a_chunk = (lg ^ ((l16 >> 2) & 3)) * 16;
+
+  f4 acc[4][8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nk = K / kV3BK;
+  v3_issue(lds, Ah, Al, Bh, Bl, K, 0, wave, lane);
+  if (nk > 1) v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, K, kV3BK, wave, lane);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    if (kt + 2 < nk) v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, K, (kt + 2) * kV3BK, wave, lane);
+    const char* st = lds + (kt % kV3Stages) * kV3Stage;
+    u4 ah[4], al[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const char* p = st + (wr + 16 * i + l16) * 64 + a_chunk;
+      ah[i] = *reinterpret_cast<const u4*>(p);
+      al[i] = *reinterpret_cast<const u4*>(p + kV3PlaneA);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int row = wc + 8 * j + (l16 >> 1);
+      const char* p = st + 2 * kV3PlaneA + row * 64 + (lg ^ ((row >> 2) & 3)) * 16;
+      u4 bh = *reinterpret_cast<const u4*>(p);
+      u4 bl = *reinterpret_cast<const u4*>(p + kV3PlaneB);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) { bh[e] = bx(bh[e]); bl[e] = bx(bl[e]); }
+      const bf8 vbh = __builtin_bit_cast(bf8, bh), vbl = __builtin_bit_cast(bf8, bl);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, al[i]), vbh, acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), vbl, acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), vbh, acc[i][j], 0, 0, 0);
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const f4 v = acc[i][j];
+      const float s0 = q ? v[0] : v[2], s1 = q ? v[1] : v[3];
+      const float r0 = __shfl_xor(s0, 1), r1 = __shfl_xor(s1, 1);
+      const int64_t row = tm * kV3BM + wr + 16 * i + 4 * lg + (q ? 2 : 0);
+      const int64_t col = tn * kV3BN + wc + 8 * j + (l16 >> 1);
+      float2 o0, o1;
+      if (q) { o0 = make_float2(r0, v[2]); o1 = make_float2(r1, v[3]); }
+      else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
+      C[row * N + col] = o0;
+      C[(row + 1) * N + col] = o1;
+    }
+}
+
+bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K) {
+  auto p2 = [](int64_t x) { return x > 0 && (x & (x - 1)) == 0; };
+  return p2(M) && p2(N) && p2(K) && M >= kV3BM && N >= kV3BN && K >= kV3BK;
+}
+
+// A, B: split operands, each a hi plane followed by a lo plane (rows x K bfloat16 pairs each),
+// batch strides in complex elements of one plane-pair (= rows * K).
+hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
+                                 float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc) {
+  if (!cgemm_presplit_fits(M, N, K)) return hipErrorInvalidValue;
+  const uint32_t* a = reinterpret_cast<const uint32_t*>(A);
+  const uint32_t* b = reinterpret_cast<const uint32_t*>(B);
+  const int64_t tiles = (M / kV3BM) * (N / kV3BN);
+  // a batch element's region holds its hi plane then its lo plane: 2 * rows * K words
+  hipLaunchKernelGGL(cgemm_v3_presplit, dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kV3Threads), 0, st, M, N, K,
+                     a, a + M * K, b, b + N * K, C, 2 * sa, 2 * sb, sc);
+  return hipGetLastError();
 }
 
 // Few outputs, long K (e.g. the last contraction of two halves into a scalar): one workgroup

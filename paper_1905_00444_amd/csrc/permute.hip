@@ -23,6 +23,7 @@ constexpr int kPermThreads = 256;
 constexpr int kPermMaxTile = 11;
 
 struct PermKernelArgs {
+  int nbits;
   int t;                    // tile bits
   int n_outer;              // outer bits
   int u_src[kPermMaxTile];  // source bit position of read-order tile bit i
@@ -38,7 +39,13 @@ struct PermKernelArgs {
   int64_t src_bstride, dst_bstride;
   const int64_t* base_table;
   int base_stride;
+  int split;
 };
+
+__device__ __forceinline__ uint32_t bf16_pair(float re, float im) {
+  const __bf16 a = (__bf16)re, b = (__bf16)im;
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
 
 __device__ __forceinline__ int lds_index(int u) { return u + (u >> 5); }
 
@@ -79,7 +86,16 @@ permute_kernel(const float2* __restrict__ src, float2* __restrict__ dst, PermKer
     float2 x = tile[lds_index(u)];
     x.x *= a.scale;
     x.y *= a.scale * a.conj_sign;
-    dst[dbase + off] = x;
+    if (a.split) {
+      // hi plane at words [0, 2^b), lo plane at [2^b, 2^(b+1)) of this batch element
+      uint32_t* w = reinterpret_cast<uint32_t*>(dst);
+      const uint32_t hi = bf16_pair(x.x, x.y);
+      const float hr = __uint_as_float(hi << 16), hiim = __uint_as_float(hi & 0xffff0000u);
+      w[dbase + off] = hi;
+      w[((int64_t)1 << a.nbits) + dbase + off] = bf16_pair(x.x - hr, x.y - hiim);
+    } else {
+      dst[dbase + off] = x;
+    }
   }
 }
 
@@ -97,6 +113,7 @@ hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const 
   for (int i = 0; i < w && t < target; ++i) if (!in_tile[i]) { in_tile[i] = 1; ++t; }
   for (int i = 0; i < b && t < target; ++i) if (!in_tile[by_src[i]]) { in_tile[by_src[i]] = 1; ++t; }
   PermKernelArgs a = {};
+  a.nbits = b;
   a.t = t;
   // read order: tile bits by ascending source position
   std::vector<int> uorder;
@@ -121,6 +138,7 @@ hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const 
   a.dst_bstride = p.dst_bstride;
   a.base_table = p.base_table;
   a.base_stride = p.base_stride;
+  a.split = p.split;
   const int64_t tiles = (int64_t)1 << no;
   const unsigned gx = (unsigned)std::min<int64_t>(tiles, 65536);
   const unsigned gy = (unsigned)(tiles / gx);

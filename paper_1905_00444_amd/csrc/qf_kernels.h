@@ -42,6 +42,9 @@ struct PermuteArgs {
   int64_t src_bstride = 0, dst_bstride = 0;
   const int64_t* base_table = nullptr;
   int base_stride = 0;
+  // split output: write bfloat16 hi = bf16(x) and lo = bf16(x - hi) of every complex number as
+  // two planes of 2^nbits packed pairs (hi plane first) in the same 8 bytes per element
+  int split = 0;
 };
 hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& a);
 
@@ -80,6 +83,11 @@ hipError_t launch_slice_accumulate_batched(hipStream_t st, const float2* root, i
                                            const int32_t* chain_b, double2* out);
 // *chain0 = value (add = 0) or *chain0 += value (add = 1), as a kernel (graph-capturable).
 hipError_t launch_chain_counter(hipStream_t st, int64_t* chain0, int64_t value, int add);
+
+// Split-BF16 GEMM on operands split by the permute (hi plane then lo plane per batch element).
+bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K);
+hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
+                                 float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc);
 
 // Batched complex GEMM, C[m][n] = sum_k A[m][k] B[n][k].
 hipError_t launch_cgemm(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K,

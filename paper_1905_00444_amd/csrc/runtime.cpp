@@ -82,6 +82,7 @@ struct Node {
 struct Operand {
   int node = -1;
   bool permute = false;
+  bool split = false;     // the permute writes split-BF16 planes for the pre-split GEMM
   std::vector<int> perm;  // dst bit i <- src bit perm[i]
   int nbits = 0;
   size_t buf = 0;         // arena offset of the permuted copy
@@ -91,6 +92,7 @@ struct Step {
   int l = -1, r = -1;
   Operand A, B;           // roles after the swap (A has the larger free volume)
   int m_bits = 0, n_bits = 0, k_bits = 0;
+  bool presplit = false;  // split-BF16 GEMM on operands split by their permutes
   double flops = 0.0;
   size_t out = 0;         // arena offset of the result
 };
@@ -523,6 +525,15 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     st.k_bits = (int)K.size();
     st.m_bits = xf;
     st.n_bits = yf;
+    st.presplit = p->precision == QF_BF16X3 && !p->backward &&
+                  cgemm_presplit_fits((int64_t)1 << xf, (int64_t)1 << yf, (int64_t)1 << K.size());
+    if (st.presplit) {
+      for (Operand* op : {&st.A, &st.B}) {
+        if (!op->permute) p->permute_bytes += 16.0 * std::ldexp(1.0, op->nbits);
+        op->permute = true;
+        op->split = true;
+      }
+    }
     st.flops = 8.0 * std::ldexp(1.0, st.m_bits + st.n_bits + st.k_bits);
     p->flops_per_slice += st.flops;
     if (out_node.dep_cuts == 0) p->flops_hoisted += st.flops;
@@ -752,6 +763,7 @@ static qf_status run_operand(qf_plan* p, const Operand& op, const uint8_t* bits_
     a.scale = 1.0f;
     src = wsp(c, nd.offset);
   }
+  a.split = op.split ? 1 : 0;
   float2* dst = wsp(c, op.buf);
   QF_HIP(c, launch_permute(c->stream, src, dst, a));
   *ptr = dst;
@@ -774,6 +786,39 @@ static qf_status plan_gemm(qf_plan* p, int64_t M, int64_t N, int64_t K, const fl
   return QF_OK;
 }
 
+// QFMI_TRACE=1: after every executed step, synchronise and print the step's shape and the largest
+// |re|, |im| of its operands and result (debugging aid; slows execution down).
+static bool trace_on() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("QFMI_TRACE");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v == 1;
+}
+
+static float trace_amax(qf_ctx* c, const float2* x, int64_t n) {
+  uint32_t* slot = reinterpret_cast<uint32_t*>(c->ws + 16);
+  if (launch_amax(c->stream, x, n, slot) != hipSuccess) return -1.f;
+  uint32_t h = 0;
+  if (hipMemcpyAsync(&h, slot, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess) return -1.f;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return -1.f;
+  float f;
+  std::memcpy(&f, &h, 4);
+  return f;
+}
+
+static void trace_step(qf_plan* p, size_t i, const float2* A, const float2* B, int64_t s) {
+  qf_ctx* c = p->ctx;
+  const Step& st = p->steps[i];
+  const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+  const float ma = st.presplit ? -2.f : trace_amax(c, A, M * K);
+  const float mb = st.presplit ? -2.f : trace_amax(c, B, N * K);
+  const float mc = trace_amax(c, wsp(c, p->nodes[p->n + i].offset), M * N);
+  std::fprintf(stderr, "qfmi trace: slice %lld step %zu (%d,%d) M=2^%d N=2^%d K=2^%d amax A %.3e B %.3e C %.3e\n",
+               (long long)s, i, st.l, st.r, st.m_bits, st.n_bits, st.k_bits, ma, mb, mc);
+}
+
 static qf_status run_step(qf_plan* p, size_t i, const uint8_t* row, int64_t s) {
   qf_ctx* c = p->ctx;
   const Step& st = p->steps[i];
@@ -792,14 +837,19 @@ static qf_status run_step(qf_plan* p, size_t i, const uint8_t* row, int64_t s) {
     e1 = take_event(c);
     if (e0 && e1) QF_HIP(c, hipEventRecord(e0, c->stream));
   }
-  e = plan_gemm(p, M, N, K, A, B, C);
-  if (e != QF_OK) return e;
+  if (st.presplit) {
+    QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, 1, M * K, N * K, M * N));
+  } else {
+    e = plan_gemm(p, M, N, K, A, B, C);
+    if (e != QF_OK) return e;
+  }
   if (timed && e0 && e1) {
     QF_HIP(c, hipEventRecord(e1, c->stream));
     c->ev_used.push_back({e0, e1});
     c->prof_flops += st.flops;
     ++c->prof_launches;
   }
+  if (trace_on()) trace_step(p, i, A, B, s);
   return QF_OK;
 }
 
@@ -842,6 +892,7 @@ static qf_status run_operand_batched(qf_plan* p, const Operand& op, const float2
     src = wsp(c, nd.offset);
     a.src_bstride = (int64_t)1 << nd.labels.size();
   }
+  a.split = op.split ? 1 : 0;
   float2* dst = wsp(c, op.buf);
   QF_HIP(c, launch_permute(c->stream, src, dst, a));
   *ptr = dst;
@@ -873,8 +924,12 @@ static qf_status enqueue_group(qf_plan* p, const uint8_t* bits_dev, int64_t s_be
       e1 = take_event(c);
       if (e0 && e1) QF_HIP(c, hipEventRecord(e0, c->stream));
     }
-    e = plan_gemm(p, M, N, K, A, B, C, G);
-    if (e != QF_OK) return e;
+    if (st.presplit) {
+      QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, G, M * K, N * K, M * N));
+    } else {
+      e = plan_gemm(p, M, N, K, A, B, C, G);
+      if (e != QF_OK) return e;
+    }
     if (timed && e0 && e1) {
       QF_HIP(c, hipEventRecord(e1, c->stream));
       c->ev_used.push_back({e0, e1});
@@ -1119,6 +1174,49 @@ qf_status qf_cgemm(qf_ctx* c, int precision, int64_t M, int64_t N, int64_t K, co
   }
   QF_HIP(c, launch_cgemm_ex(c->stream, precision, M, N, K, reinterpret_cast<const float2*>(A),
                             reinterpret_cast<const float2*>(B), reinterpret_cast<float2*>(C), batch, sa, sb, sc, amA, amB));
+  return QF_OK;
+}
+
+qf_status qf_split_bf16(qf_ctx* c, const void* src, void* dst, int nbits) {
+  if (!c || !src || !dst || nbits < 0 || nbits > 40) return fail(c, QF_ERR_ARG, "qf_split_bf16: bad arguments");
+  PermuteArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nbits = nbits;
+  for (int i = 0; i < nbits; ++i) a.perm[i] = i;
+  a.scale = 1.0f;
+  a.split = 1;
+  QF_HIP(c, launch_permute(c->stream, reinterpret_cast<const float2*>(src), reinterpret_cast<float2*>(dst), a));
+  return QF_OK;
+}
+
+qf_status qf_cgemm_presplit(qf_ctx* c, int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C) {
+  if (!c || !A || !B || !C) return fail(c, QF_ERR_ARG, "qf_cgemm_presplit: null pointer");
+  if (!cgemm_presplit_fits(M, N, K))
+    return fail(c, QF_ERR_UNSUPPORTED, "qf_cgemm_presplit needs powers of two with M >= 256, N >= 128, K >= 16");
+  QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, reinterpret_cast<float2*>(C), 1, M * K, N * K, M * N));
+  return QF_OK;
+}
+
+qf_status qf_time_cgemm_presplit(qf_ctx* c, int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C,
+                                 int reps, float* ms) {
+  if (!c || !ms || reps < 1) return QF_ERR_ARG;
+  qf_status st = qf_cgemm_presplit(c, M, N, K, A, B, C);
+  if (st != QF_OK) return st;
+  hipEvent_t e0, e1;
+  QF_HIP(c, hipEventCreate(&e0));
+  QF_HIP(c, hipEventCreate(&e1));
+  QF_HIP(c, hipEventRecord(e0, c->stream));
+  for (int i = 0; i < reps; ++i) {
+    st = qf_cgemm_presplit(c, M, N, K, A, B, C);
+    if (st != QF_OK) return st;
+  }
+  QF_HIP(c, hipEventRecord(e1, c->stream));
+  QF_HIP(c, hipEventSynchronize(e1));
+  float t = 0.f;
+  QF_HIP(c, hipEventElapsedTime(&t, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms = t / reps;
   return QF_OK;
 }
 

@@ -167,7 +167,7 @@ def _product_slice_closed_form(circ, plan, bits_row, s):
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16"])
 def test_product_circuit_full_7x7_d40_shape_one_slice(ctx, precision):
     """Every tensor of the 7x7 (1+40+1) workload at full size (peak 2^30), CZ -> identity."""
     _say(f"7x7 d40 product circuit, slice 37, {precision}")
@@ -194,3 +194,29 @@ def test_mirror_circuit_7x7_bond16_all_slices(ctx, precision):
     want = np.zeros(64, dtype=np.complex128)
     want[0] = 1.0
     assert np.max(np.abs(got - want)) <= (2e-5 if precision == "fp32" else 2e-4)
+
+
+def test_product_circuit_7x7_d40_bench_launch_configuration(ctx):
+    """The benchmark's exact call: one prefix, slices 0..5 with reuse of the subtrees that do not
+    depend on the second cut, split-BF16; every slice has a closed form when CZ -> identity."""
+    _say("7x7 d40 product circuit, slices 0..5 (bench configuration)")
+    base = generate(7, 7, 40, 0)
+    plan, _ = plan_7x7(base, 40)
+    c = identity_cz(base)
+    bits = random_bitstrings(1, 49, 1)
+    got = _amps(ctx, c, plan, bits, "bf16x3", 0, 6)[0]
+    ref = sum(_product_slice_closed_form(c, plan, bits[0], s) for s in range(6))
+    assert rel_err(got, ref) <= 1e-4
+
+
+def test_7x7_d32_random_slice_vs_tensor_network_oracle(ctx):
+    """A random 7x7 (1+32+1) circuit (bond 16, peak 2^28): one slice of one prefix (64
+    amplitudes) against the FP64 tensor-network oracle, FP32 and split-BF16."""
+    _say("7x7 d32 random slice vs oracle-TN")
+    c = generate(7, 7, 32, 0)
+    plan, _ = plan_7x7(c, 32)
+    bits = random_bitstrings(1, 49, 1)
+    ref = tn.amplitudes(c.to_text(), bits, plan, slices=[3])
+    for prec, bound in (("fp32", 1e-5), ("bf16x3", 1e-4)):
+        got = _amps(ctx, c, plan, bits, prec, 3, 4)
+        assert rel_err(got, ref) <= bound, prec

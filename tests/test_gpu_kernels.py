@@ -117,3 +117,47 @@ def test_cgemm_rejects_bad_arguments(ctx):
     assert st == _lib.QF_ERR_ARG
     st = ctx.lib.qf_cgemm(ctx.h, 7, 4, 4, 4, Cc.c_void_p(256), Cc.c_void_p(256), Cc.c_void_p(256), 1, 0, 0, 0)
     assert st == _lib.QF_ERR_ARG
+
+
+def test_split_bf16_matches_torch_rounding(ctx):
+    """hi = bf16(x) and lo = bf16(x - hi), round-to-nearest-even, bit-exact vs torch's conversion."""
+    import torch
+    from paper_1905_00444_amd import split_bf16
+    _say("split bf16")
+    rng = np.random.default_rng(11)
+    x = _rand_c64(rng, 2 ** 14) * np.float32(3.7)
+    xt = torch.from_numpy(x).cuda()
+    s = split_bf16(ctx, xt)
+    torch.cuda.synchronize()
+    w = s.cpu().numpy().view(np.uint32)
+    n = x.size
+    re = torch.from_numpy(x.real.copy()).to(torch.bfloat16)
+    im = torch.from_numpy(x.imag.copy()).to(torch.bfloat16)
+    hi_re = re.view(torch.int16).numpy().view(np.uint16).astype(np.uint32)
+    hi_im = im.view(torch.int16).numpy().view(np.uint16).astype(np.uint32)
+    assert np.array_equal(w[:n] & 0xFFFF, hi_re) and np.array_equal(w[:n] >> 16, hi_im)
+    lo_re = torch.from_numpy(x.real - re.float().numpy()).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(w[n:] & 0xFFFF, lo_re.astype(np.uint32))
+    # hi + lo reconstructs x to about 2^-16 relative
+    def f(u):
+        return (u.astype(np.uint32) << 16).view(np.float32)
+    rec = f(w[:n] & 0xFFFF) + f(w[n:] & 0xFFFF)
+    assert np.max(np.abs(rec - x.real) / (np.abs(x.real) + 1e-30)) <= 2.0 ** -15
+
+
+@pytest.mark.parametrize("M,N,K", [(256, 128, 16), (512, 256, 64), (1024, 512, 2048), (2048, 1024, 512)])
+def test_cgemm_presplit_matches_numpy(ctx, M, N, K):
+    import torch
+    from paper_1905_00444_amd import split_bf16, cgemm_presplit
+    _say(f"cgemm presplit {M}x{N}x{K}")
+    rng = np.random.default_rng(M + N + K)
+    A = _rand_c64(rng, (M, K))
+    B = _rand_c64(rng, (N, K))
+    ref = A.astype(np.complex128) @ B.astype(np.complex128).T
+    bound = np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64).T
+    As = split_bf16(ctx, torch.from_numpy(A).cuda().reshape(-1))
+    Bs = split_bf16(ctx, torch.from_numpy(B).cuda().reshape(-1))
+    Cg = cgemm_presplit(ctx, As, Bs, M, N, K)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(Cg.cpu().numpy().astype(np.complex128) - ref) / bound)
+    assert err <= TOL["bf16x3"], err
