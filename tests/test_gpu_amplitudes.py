@@ -9,7 +9,7 @@ from oracle import sv, tn
 from oracle.metrics import rel_err
 from workloads.bitstrings import random_bitstrings, all_bitstrings
 from workloads.circuits import generate, identity_cz, mirror
-from workloads.plans import sweep_plan, region_plan, plan_7x7
+from workloads.plans import sweep_plan, region_plan, plan_7x7, nonvanishing_slices
 
 pytestmark = pytest.mark.gpu
 
@@ -175,9 +175,10 @@ def test_product_circuit_full_7x7_d40_shape_one_slice(ctx, precision):
     plan, _ = plan_7x7(base, 40)
     c = identity_cz(base)
     bits = random_bitstrings(1, 49, 1)
-    s = 37
-    got = _amps(ctx, c, plan, bits, precision, s, s + 1)[0]
+    s = nonvanishing_slices(base, plan, bits[0], 3)[-1]
     ref = _product_slice_closed_form(c, plan, bits[0], s)
+    assert np.linalg.norm(ref) > 1e-20
+    got = _amps(ctx, c, plan, bits, precision, s, s + 1)[0]
     assert rel_err(got, ref) <= BOUND[precision]
 
 
@@ -204,8 +205,11 @@ def test_product_circuit_7x7_d40_bench_launch_configuration(ctx):
     plan, _ = plan_7x7(base, 40)
     c = identity_cz(base)
     bits = random_bitstrings(1, 49, 1)
-    got = _amps(ctx, c, plan, bits, "bf16x3", 0, 6)[0]
-    ref = sum(_product_slice_closed_form(c, plan, bits[0], s) for s in range(6))
+    sl = nonvanishing_slices(base, plan, bits[0], 6)
+    assert sl == list(range(sl[0], sl[0] + 6))
+    got = _amps(ctx, c, plan, bits, "bf16x3", sl[0], sl[0] + 6)[0]
+    ref = sum(_product_slice_closed_form(c, plan, bits[0], s) for s in sl)
+    assert np.linalg.norm(ref) > 1e-20
     assert rel_err(got, ref) <= 1e-4
 
 
@@ -216,7 +220,9 @@ def test_7x7_d32_random_slice_vs_tensor_network_oracle(ctx):
     c = generate(7, 7, 32, 0)
     plan, _ = plan_7x7(c, 32)
     bits = random_bitstrings(1, 49, 1)
-    ref = tn.amplitudes(c.to_text(), bits, plan, slices=[3])
+    s = nonvanishing_slices(c, plan, bits[0], 4)[-1]
+    ref = tn.amplitudes(c.to_text(), bits, plan, slices=[s])
+    assert np.linalg.norm(ref) > 1e-20
     for prec, bound in (("fp32", 1e-5), ("bf16x3", 1e-4)):
-        got = _amps(ctx, c, plan, bits, prec, 3, 4)
+        got = _amps(ctx, c, plan, bits, prec, s, s + 1)
         assert rel_err(got, ref) <= bound, prec

@@ -54,3 +54,29 @@ def test_7x7_plan_shapes():
     c3 = generate(7, 7, 32, 0)
     plan3, pb3 = plan_7x7(c3, 32)
     assert max(pb3.sizes()) == 28
+
+
+def test_structurally_vanishing_slices_are_zero_in_the_oracle():
+    """Slices the gate-name rules declare vanishing are zero in the FP64 oracle (up to rounding),
+    and the others are not, on a small grid with a cut that has both kinds of constraint."""
+    import numpy as np
+    from oracle import tn
+    from workloads.bitstrings import random_bitstrings
+    from workloads.plans import slice_vanishes, _cut_rules, sweep_plan
+    found = False
+    for seed in range(12):
+        c = generate(3, 3, 16, seed)
+        qid = c.qubit_of()
+        for (a, b) in (((0, 1), (0, 2)), ((1, 1), (1, 2)), ((0, 2), (1, 2)), ((1, 0), (2, 0))):
+            q0, q1 = sorted((qid[a], qid[b]))
+            ties, tail = _cut_rules(c, q0, q1)
+            if ties or tail:
+                plan = sweep_plan(c, cuts=[[q0, q1, 0, 2]])
+                bits = random_bitstrings(2, 9, seed)
+                for row in bits:
+                    for s in range(4):
+                        v = tn.amplitudes(c.to_text(), row[None], plan, slices=[s])
+                        if slice_vanishes(c, plan, row, s):
+                            assert np.abs(v).max() < 1e-14
+                            found = True
+    assert found

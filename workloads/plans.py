@@ -161,6 +161,65 @@ def region_plan(circ: Circuit, split_row: int, split_col: int, cuts: Sequence[Se
     return pb.plan(), pb
 
 
+# --- structural zeros of slices ------------------------------------------------
+#
+# Fixing a cut bond bit fixes, on the bond's lower-numbered qubit q0, a projection onto |k> at
+# that gate's time (a diagonal gate is split as sum_k |k><k|_q0 (x) diag(.)_q1).  Two rules make
+# a slice vanish identically, read off the gate names alone:
+#   * only diagonal gates act on q0 between two consecutive projections of the same cut bond:
+#     the two bits must agree;
+#   * after the bond's last projection q0 sees only diagonal gates, then sqrt(Y), then the final
+#     H: H sqrt(Y) maps |k> to a multiple of |k>, so the last bit must equal q0's output bit.
+# A fidelity-f pass (a fraction of the paths) should compute paths that are not forced to zero.
+
+DIAGONAL_GATES = {"t", "s", "tdg", "sdg", "cz", "id2"}
+
+
+def _cut_rules(circ: Circuit, q0: int, q1: int):
+    """(ties, tail) for a cut bond: ties = pairs (j, j+1) of bond bits that must agree;
+    tail = True if the last bond bit must equal q0's output bit."""
+    ops = [op for op in circ.ops if q0 in op.qubits]
+    idx = [i for i, op in enumerate(ops) if op.qubits == (q0, q1)]
+    ties = []
+    for j, (a, b) in enumerate(zip(idx, idx[1:])):
+        if all(op.name in DIAGONAL_GATES for op in ops[a + 1:b]):
+            ties.append((j, j + 1))
+    rest = [op.name for op in ops[idx[-1] + 1:] if op.name not in DIAGONAL_GATES] if idx else []
+    tail = rest == ["y_1_2", "h"]
+    return ties, tail
+
+
+def slice_vanishes(circ: Circuit, plan: dict, bits_row, s: int) -> bool:
+    """True if the rules above force slice s of `plan` to contribute zero for this prefix."""
+    cuts = plan.get("cuts", [])
+    total = sum(c[3] for c in cuts)
+    off = total
+    for q0, q1, lo, nb in cuts:
+        off -= nb
+        v = (s >> off) & ((1 << nb) - 1)
+        bit = {lo + i: (v >> (nb - 1 - i)) & 1 for i in range(nb)}
+        ties, tail = _cut_rules(circ, q0, q1)
+        for a, b in ties:
+            if a in bit and b in bit and bit[a] != bit[b]:
+                return True
+        n_bond = sum(1 for op in circ.ops if op.qubits == (q0, q1))
+        if tail and (n_bond - 1) in bit and q0 not in plan.get("open", []) and bit[n_bond - 1] != int(bits_row[q0]):
+            return True
+    return False
+
+
+def nonvanishing_slices(circ: Circuit, plan: dict, bits_row, count: int, start: int = 0):
+    """The first `count` slices at or after `start` not forced to zero (slice_vanishes)."""
+    n_slices = 1 << sum(c[3] for c in plan.get("cuts", []))
+    out = []
+    for s in range(start, n_slices):
+        if not slice_vanishes(circ, plan, bits_row, s):
+            out.append(s)
+            if len(out) == count:
+                break
+    return out
+
+
 # --- the benchmark workloads -------------------------------------------------
 
 C4_OPEN_SITES = ((5, 4), (5, 5), (5, 6), (6, 4), (6, 5), (6, 6))
@@ -171,7 +230,9 @@ def plan_7x7(circ: Circuit, depth: int) -> Tuple[dict, PlanBuilder]:
 
     depth 32 (bond 16): one whole cut on (6,2)-(6,3) -> 16 slices.
     depth 40 (bond 32): whole cuts on (2,6)-(3,6) and (6,2)-(6,3) -> 1024 slices.
-    Six output qubits in the bottom-right corner stay open (64 amplitudes/pass).
+    These corner bonds keep the largest tensor at 2^30 (2^28); a cut further inside the
+    boundary leaves a hole that grows the region-C frontier to 2^35.  Six output qubits in the
+    bottom-right corner stay open (64 amplitudes per pass).
     """
     qid = circ.qubit_of()
     nb = depth // 8
