@@ -201,7 +201,7 @@ qf_status qf_ctx_set_stream(qf_ctx* ctx, void* hip_stream) {
 void qf_ctx_destroy(qf_ctx* ctx) {
   if (!ctx) return;
   for (auto& p : ctx->ev_used) { ctx->ev_pool.push_back(p.first); ctx->ev_pool.push_back(p.second); }
-  for (auto e : ctx->ev_pool) hipEventDestroy(e);
+  for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -627,9 +627,9 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
 void qf_plan_destroy(qf_plan* plan) {
   if (plan && plan->ctx && plan->ctx->last_built == plan) plan->ctx->last_built = nullptr;
   if (plan && plan->gexec) {
-    hipStreamSynchronize(plan->ctx->stream);
-    hipGraphExecDestroy(plan->gexec);
-    hipGraphDestroy(plan->graph_obj);
+    (void)hipStreamSynchronize(plan->ctx->stream);
+    (void)hipGraphExecDestroy(plan->gexec);
+    (void)hipGraphDestroy(plan->graph_obj);
   }
   delete plan;
 }
@@ -964,8 +964,8 @@ static qf_status amplitudes_batched(qf_plan* p, int n_batch, const uint8_t* bits
   if (!p->gexec || key != p->graph_key) {
     if (p->gexec) {
       QF_HIP(c, hipStreamSynchronize(c->stream));
-      hipGraphExecDestroy(p->gexec);
-      hipGraphDestroy(p->graph_obj);
+      (void)hipGraphExecDestroy(p->gexec);
+      (void)hipGraphDestroy(p->graph_obj);
       p->gexec = nullptr;
       p->graph_obj = nullptr;
     }
@@ -974,14 +974,14 @@ static qf_status amplitudes_batched(qf_plan* p, int n_batch, const uint8_t* bits
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(c->stream, &graph);
     if (e != QF_OK) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       return e;
     }
     if (ce != hipSuccess) return hip_fail(c, ce, "hipStreamEndCapture");
     hipGraphExec_t exec = nullptr;
     ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (ce != hipSuccess) {
-      hipGraphDestroy(graph);
+      (void)hipGraphDestroy(graph);
       return hip_fail(c, ce, "hipGraphInstantiate");
     }
     p->gexec = exec;
@@ -1214,8 +1214,8 @@ qf_status qf_time_cgemm_presplit(qf_ctx* c, int64_t M, int64_t N, int64_t K, con
   QF_HIP(c, hipEventSynchronize(e1));
   float t = 0.f;
   QF_HIP(c, hipEventElapsedTime(&t, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   *ms = t / reps;
   return QF_OK;
 }
@@ -1243,8 +1243,8 @@ qf_status qf_time_cgemm(qf_ctx* c, int precision, int64_t M, int64_t N, int64_t 
   QF_HIP(c, hipEventSynchronize(e1));
   float t = 0.f;
   QF_HIP(c, hipEventElapsedTime(&t, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   *ms = t / reps;
   return QF_OK;
 }
@@ -1265,8 +1265,8 @@ qf_status qf_time_permute(qf_ctx* c, const void* src, void* dst, int nbits, cons
   QF_HIP(c, hipEventSynchronize(e1));
   float t = 0.f;
   QF_HIP(c, hipEventElapsedTime(&t, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   *ms = t / reps;
   return QF_OK;
 }
