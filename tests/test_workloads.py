@@ -58,25 +58,29 @@ def test_7x7_plan_shapes():
 
 def test_structurally_vanishing_slices_are_zero_in_the_oracle():
     """Slices the gate-name rules declare vanishing are zero in the FP64 oracle (up to rounding),
-    and the others are not, on a small grid with a cut that has both kinds of constraint."""
+    over many seeds, depths and bonds so that both rules fire."""
     import numpy as np
     from oracle import tn
     from workloads.bitstrings import random_bitstrings
     from workloads.plans import slice_vanishes, _cut_rules, sweep_plan
-    found = False
-    for seed in range(12):
-        c = generate(3, 3, 16, seed)
-        qid = c.qubit_of()
-        for (a, b) in (((0, 1), (0, 2)), ((1, 1), (1, 2)), ((0, 2), (1, 2)), ((1, 0), (2, 0))):
-            q0, q1 = sorted((qid[a], qid[b]))
-            ties, tail = _cut_rules(c, q0, q1)
-            if ties or tail:
-                plan = sweep_plan(c, cuts=[[q0, q1, 0, 2]])
+    fired = {"tie": 0, "tail": 0}
+    for depth in (8, 16):
+        for seed in range(16):
+            c = generate(3, 3, depth, seed)
+            qid = c.qubit_of()
+            for (a, b) in (((0, 0), (0, 1)), ((0, 1), (0, 2)), ((1, 1), (1, 2)), ((0, 2), (1, 2)),
+                           ((1, 0), (2, 0)), ((1, 1), (2, 1))):
+                q0, q1 = sorted((qid[a], qid[b]))
+                ties, tail = _cut_rules(c, q0, q1)
+                if not (ties or tail):
+                    continue
+                nb = depth // 8
+                plan = sweep_plan(c, cuts=[[q0, q1, 0, nb]])
                 bits = random_bitstrings(2, 9, seed)
                 for row in bits:
-                    for s in range(4):
-                        v = tn.amplitudes(c.to_text(), row[None], plan, slices=[s])
+                    for s in range(2 ** nb):
                         if slice_vanishes(c, plan, row, s):
-                            assert np.abs(v).max() < 1e-14
-                            found = True
-    assert found
+                            v = tn.amplitudes(c.to_text(), row[None], plan, slices=[s])
+                            assert np.abs(v).max() < 1e-14, (depth, seed, a, b, s)
+                            fired["tie" if ties else "tail"] += 1
+    assert fired["tie"] > 0 and fired["tail"] > 0, fired

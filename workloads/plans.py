@@ -168,8 +168,10 @@ def region_plan(circ: Circuit, split_row: int, split_col: int, cuts: Sequence[Se
 # a slice vanish identically, read off the gate names alone:
 #   * only diagonal gates act on q0 between two consecutive projections of the same cut bond:
 #     the two bits must agree;
-#   * after the bond's last projection q0 sees only diagonal gates, then sqrt(Y), then the final
-#     H: H sqrt(Y) maps |k> to a multiple of |k>, so the last bit must equal q0's output bit.
+#   * after the bond's last projection q0 sees only diagonal gates, then sqrt(Y) immediately
+#     followed by the final H: H sqrt(Y) maps |k> to a multiple of |k>, so the last bit must
+#     equal q0's output bit.  (A diagonal gate between sqrt(Y) and H would change that: a CZ
+#     factor there flips the sign of |1> depending on another bond, a T rotates it.)
 # A fidelity-f pass (a fraction of the paths) should compute paths that are not forced to zero.
 
 DIAGONAL_GATES = {"t", "s", "tdg", "sdg", "cz", "id2"}
@@ -184,8 +186,12 @@ def _cut_rules(circ: Circuit, q0: int, q1: int):
     for j, (a, b) in enumerate(zip(idx, idx[1:])):
         if all(op.name in DIAGONAL_GATES for op in ops[a + 1:b]):
             ties.append((j, j + 1))
-    rest = [op.name for op in ops[idx[-1] + 1:] if op.name not in DIAGONAL_GATES] if idx else []
-    tail = rest == ["y_1_2", "h"]
+    tail = False
+    if idx:
+        rest = [op.name for op in ops[idx[-1] + 1:]]
+        nondiag = [i for i, name in enumerate(rest) if name not in DIAGONAL_GATES]
+        tail = (len(nondiag) == 2 and rest[nondiag[0]] == "y_1_2" and rest[nondiag[1]] == "h"
+                and nondiag[1] == nondiag[0] + 1)
     return ties, tail
 
 
