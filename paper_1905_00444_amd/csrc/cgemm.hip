@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>
+#include <algorithm>
 #include "qf_kernels.h"
 
 namespace qf {
@@ -638,6 +639,46 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
   return hipGetLastError();
 }
 
+// Short K, narrow N, long M (a large tensor absorbing one small world-line): B (N x K) is staged
+// in LDS; thread t computes outputs (m, 4g .. 4g+3) with m = t / (N/4), so consecutive threads
+// write consecutive 32-byte groups of C and the threads sharing a row read the same A row.
+constexpr int kSkinnyMaxB = 4096;  // complex elements of B held in LDS
+
+__global__ void __launch_bounds__(256)
+cgemm_skinny(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
+             float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc) {
+  __shared__ float2 Bs[kSkinnyMaxB];
+  const int64_t batch = blockIdx.z;
+  A += batch * sa;
+  B += batch * sb;
+  C += batch * sc;
+  const int nk = (int)(N * K);
+  for (int i = threadIdx.x; i < nk; i += 256) Bs[i] = B[i];
+  __syncthreads();
+  const int64_t groups = N / 4;
+  const int64_t total = M * groups;
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < total; o += (int64_t)gridDim.x * 256) {
+    const int64_t m = o / groups;
+    const int g = (int)(o - m * groups);
+    const float2* a = A + m * K;
+    float cr[4] = {0.f, 0.f, 0.f, 0.f}, ci[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < (int)K; ++k) {
+      const float2 x = a[k];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float2 y = Bs[(4 * g + t) * K + k];
+        cr[t] = fmaf(x.x, y.x, cr[t]);
+        cr[t] = fmaf(-x.y, y.y, cr[t]);
+        ci[t] = fmaf(x.x, y.y, ci[t]);
+        ci[t] = fmaf(x.y, y.x, ci[t]);
+      }
+    }
+    float4* out = reinterpret_cast<float4*>(C + m * N + 4 * g);
+    out[0] = make_float4(cr[0], ci[0], cr[1], ci[1]);
+    out[1] = make_float4(cr[2], ci[2], cr[3], ci[3]);
+  }
+}
+
 // Few outputs, long K (e.g. the last contraction of two halves into a scalar): one workgroup
 // per output element, threads stride over K, then a workgroup reduction.
 __global__ void __launch_bounds__(256)
@@ -718,6 +759,12 @@ hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, 
   const bool p2 = pow2(M) && pow2(N) && pow2(K);
   const bool big = p2 && precision != P_FP32 && use_v2() && M >= kV2BM && N >= kV2BN && K >= kV2BK;
   const bool tiled = big || (p2 && M >= 32 && N >= 32 && K >= kBK);
+  if (!tiled && N >= 4 && N * K <= kSkinnyMaxB && K <= 64 && (N & 3) == 0) {
+    const int64_t total = M * (N / 4);
+    unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(cgemm_skinny, dim3(blocks, 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C, sa, sb, sc);
+    return hipGetLastError();
+  }
   if (!tiled && M * N <= 4096 && K >= 256) {
     hipLaunchKernelGGL(cgemm_splitk, dim3((unsigned)(M * N), 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C,
                        sa, sb, sc);

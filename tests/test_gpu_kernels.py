@@ -69,7 +69,8 @@ def test_permute_gather_with_fixed_bits(ctx, b, extra):
 
 
 SHAPES = [(1, 1, 1), (3, 5, 7), (16, 8, 4), (32, 32, 32), (64, 32, 64), (128, 64, 32), (256, 128, 512), (256, 128, 16),
-          (1024, 64, 256), (512, 512, 2048), (2048, 1024, 128), (1, 1, 65536), (4, 8, 4096), (3, 2, 1000)]
+          (1024, 64, 256), (512, 512, 2048), (2048, 1024, 128), (1, 1, 65536), (4, 8, 4096), (3, 2, 1000),
+          (32768, 64, 8), (4096, 8, 16), (65536, 4, 4), (8192, 16, 64)]
 TOL = {"fp32": 2e-6, "bf16x3": 3e-5, "fp16": 3e-3}
 
 
