@@ -76,8 +76,16 @@ enum {
                            subtrees across slices) */
   QF_PLAN_BACKWARD = 2, /* keep every forward tensor and reserve environment buffers so that
                            qf_backward can run (implies QF_PLAN_NO_HOIST; larger workspace) */
-  QF_PLAN_GRAPH = 4     /* batched plans: capture one group's launches in a hipGraph and replay it
+  QF_PLAN_GRAPH = 4,    /* batched plans: capture one group's launches in a hipGraph and replay it
                            for every group (needs a non-null stream) */
+  QF_PLAN_NO_RENORM = 8 /* store every intermediate at its true scale.  By default (Sec. III-E:
+                           normalise the inputs, renormalise at the end) each stored tensor keeps
+                           a power-of-two exponent on the device: a contraction divides its
+                           result by 2^(e_A + e_B), e_X the binary exponent of operand X's
+                           largest |re|, |im|, adds e_A + e_B to the result's exponent, and the
+                           slice sum multiplies by 2^E in FP64.  Exact in binary floating point;
+                           keeps amplitudes of 2^-n scale (and far smaller slices) away from FP32
+                           and FP16 underflow.  Backward plans always store true scales. */
 };
 
 /* Contraction plan.  steps: 2*n_steps node ids (lhs, rhs) in execution order.  Ids 0..n-1

@@ -16,6 +16,7 @@ QF_OP_1Q, QF_OP_2Q_DIAG = 1, 2
 QF_PLAN_NO_HOIST = 1
 QF_PLAN_BACKWARD = 2
 QF_PLAN_GRAPH = 4
+QF_PLAN_NO_RENORM = 8
 
 STATUS_NAMES = {0: "QF_OK", -1: "QF_ERR_ARG", -2: "QF_ERR_PLAN", -3: "QF_ERR_WORKSPACE", -4: "QF_ERR_HIP",
                 -5: "QF_ERR_UNSUPPORTED", -6: "QF_ERR_INJECTED"}

@@ -134,7 +134,9 @@ class Circuit:
 
 class Plan:
     def __init__(self, ctx: Context, circuit: Circuit, plan: dict, precision: str = "fp32", hoist: bool = True,
-                 backward: bool = False, batch: int = 1, graph: bool = False):
+                 backward: bool = False, batch: int = 1, graph: bool = False, renorm: bool = True):
+        """renorm: keep a power-of-two exponent per stored tensor on the device (default); False
+        stores every tensor at its true scale (backward plans always do)."""
         self.ctx = ctx
         self.circuit = circuit
         self.plan = plan
@@ -155,7 +157,7 @@ class Plan:
         d.open = opn.ctypes.data_as(C.POINTER(C.c_int32)) if len(opn) else None
         d.precision = PRECISIONS[precision]
         d.flags = ((0 if hoist else _lib.QF_PLAN_NO_HOIST) | (_lib.QF_PLAN_BACKWARD if backward else 0)
-                   | (_lib.QF_PLAN_GRAPH if graph else 0))
+                   | (_lib.QF_PLAN_GRAPH if graph else 0) | (0 if renorm else _lib.QF_PLAN_NO_RENORM))
         d.batch = int(batch)
         h = C.c_void_p()
         check(ctx.lib.qf_plan_create(ctx.h, circuit.h, C.byref(d), C.byref(h)), ctx.h)

@@ -15,8 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-OUT = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "libqfmi.so")
+OUT = os.environ.get("QFMI_BUILD_DIR", os.path.join(HERE, "_build"))
+LIB = os.environ.get("QFMI_LIB_OUT", os.path.join(HERE, "libqfmi.so"))
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -16,8 +16,15 @@
 //            relative, is dropped).
 //   FP16   : x * 2^s rounded to fp16 with s chosen from the operand's max magnitude so the
 //            largest entry lands near 2^14; v_mfma_f32_16x16x32_f16, FP32 accumulation; the
-//            epilogue multiplies by 2^-(sA+sB), which is exact (paper Sec. III-E: normalise the
-//            inputs, renormalise at the end).
+//            epilogue multiplies by 2^-(sA+sB), which is exact.
+//
+// Renormalisation (paper Sec. III-E: normalise the inputs, renormalise at the end), done with
+// powers of two so that it is exact: every stored tensor X carries a device-side exponent E_X
+// (true values = stored * 2^E_X) and the max magnitude of its stored values.  A renormalised
+// GEMM stores C * 2^-(e_A + e_B), e_X the binary exponent of X's max magnitude, so stored
+// values stay near 1 whatever the true scale; E_C = E_A + E_B + e_A + e_B is written by one
+// thread, C's max magnitude is gathered in the epilogue (one atomic max per wave), and the FP64
+// slice sum applies 2^E of the root.
 //
 // Tiling: 256 threads = 4 waves as 2 x 2; a wave owns WTM x WTN MFMA tiles of 16 rows x 16 real
 // columns (8 complex); block tile BM = 32 WTM rows x BN = 16 WTN complex columns; K-tiles of
@@ -62,6 +69,53 @@ __device__ __forceinline__ int fp16_shift(const uint32_t* amax) {
   int e;
   frexpf(m, &e);  // m = f * 2^e, f in [0.5, 1)
   return 14 - e;
+}
+
+// Binary exponent e of a stored tensor's max magnitude (amax = f 2^e, f in [0.5, 1)), clamped so
+// that the epilogue factor 2^-(e_A + e_B) stays a normal float; 0 for an all-zero tensor.
+__device__ __forceinline__ int renorm_exp(const NodeScale* n) {
+  const float m = __uint_as_float(n->amax);
+  if (!(m > 0.f) || !(m <= 3.0e38f)) return 0;
+  int e;
+  frexpf(m, &e);
+  return e < -62 ? -62 : (e > 62 ? 62 : e);
+}
+
+// Operand scales for staging (FP16 only) and the epilogue factor.  Renormalised: FP16 operands are
+// brought to max ~2^14 from their exponents, the result is stored times 2^-(e_A + e_B), and
+// thread 0 of the first workgroup writes the result's exponent.  Otherwise FP16 scales from the
+// given max magnitudes and undoes them in the epilogue; FP32 / BF16 use no scaling.
+template <int PREC>
+__device__ __forceinline__ void renorm_begin(const Renorm& rn, const uint32_t* amaxA, const uint32_t* amaxB,
+                                             float& scale_a, float& scale_b, float& unscale) {
+  int s_a = 0, s_b = 0, e_ab = 0;
+  if (rn.c) {
+    const int ea = renorm_exp(rn.a), eb = renorm_exp(rn.b);
+    e_ab = ea + eb;
+    if constexpr (PREC == P_FP16) {
+      s_a = 14 - ea;
+      s_b = 14 - eb;
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) rn.c->e = rn.a->e + rn.b->e + e_ab;
+  } else if constexpr (PREC == P_FP16) {
+    s_a = fp16_shift(amaxA);
+    s_b = fp16_shift(amaxB);
+  }
+  scale_a = ldexpf(1.f, s_a);
+  scale_b = ldexpf(1.f, s_b);
+  unscale = ldexpf(1.f, -(s_a + s_b + e_ab));
+}
+
+__device__ __forceinline__ float cmax(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
+
+// Wave-wide max of m, one atomic per wave into c->amax (every lane of the wave must call).
+__device__ __forceinline__ void record_amax(NodeScale* c, float m) {
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(&c->amax, __float_as_uint(m));
+}
+
+__global__ void renorm_reset(NodeScale* c) {
+  if (threadIdx.x == 0) c->amax = 0u;
 }
 
 template <int PREC>
@@ -131,7 +185,7 @@ template <int PREC, int WTM, int WTN>
 __global__ void __launch_bounds__(kThreads)
 cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
            float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, const uint32_t* amaxA,
-           const uint32_t* amaxB) {
+           const uint32_t* amaxB, Renorm rn) {
   constexpr int BM = 32 * WTM, BN = 16 * WTN;
   using LA = TileLds<PREC, BM>;
   using LB = TileLds<PREC, BN>;
@@ -162,13 +216,8 @@ cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
   const int wc = (wave & 1) * (8 * WTN);     // wave's first complex column
   const int l16 = lane & 15, lg = lane >> 4;
 
-  float scale_a = 1.f, scale_b = 1.f, unscale = 1.f;
-  if constexpr (PREC == P_FP16) {
-    const int s_a = fp16_shift(amaxA), s_b = fp16_shift(amaxB);
-    scale_a = ldexpf(1.f, s_a);
-    scale_b = ldexpf(1.f, s_b);
-    unscale = ldexpf(1.f, -(s_a + s_b));
-  }
+  float scale_a, scale_b, unscale;
+  renorm_begin<PREC>(rn, amaxA, amaxB, scale_a, scale_b, unscale);
 
   f4 acc[WTM][WTN];
 #pragma unroll
@@ -256,6 +305,7 @@ cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
   // Epilogue: lane holds real column (n, q = l16 & 1) for rows 4*lg .. 4*lg+3 of each tile.
   // Exchange with the partner lane (l ^ 1) so each lane owns two complex results.
   const int q = l16 & 1;
+  float mx = 0.f;
 #pragma unroll
   for (int i = 0; i < WTM; ++i)
 #pragma unroll
@@ -270,7 +320,9 @@ cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
       else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
       C[row * N + col] = o0;
       C[(row + 1) * N + col] = o1;
+      mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
     }
+  if (rn.c) record_amax(rn.c, mx);
 }
 
 // Large shapes, BF16-family products: 512 threads = 8 waves as 4 (M) x 2 (N); a wave owns
@@ -348,7 +400,8 @@ __device__ __forceinline__ void v2_load(float4 (&ra)[4], float4 (&rb)[2], const 
 template <int PREC>
 __global__ void __launch_bounds__(kV2Threads)
 cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
-         float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, const uint32_t* amaxA, const uint32_t* amaxB) {
+         float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, const uint32_t* amaxA, const uint32_t* amaxB,
+         Renorm rn) {
   __shared__ __attribute__((aligned(16))) char lds[2 * V2<PREC>::stage];
   constexpr int planes = V2<PREC>::planes;
 
@@ -375,13 +428,8 @@ cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const fl
   const int l16 = lane & 15, lg = lane >> 4, q = l16 & 1;
   const BExpand bx(q);
 
-  float scale_a = 1.f, scale_b = 1.f, unscale = 1.f;
-  if constexpr (PREC == P_FP16) {
-    const int s_a = fp16_shift(amaxA), s_b = fp16_shift(amaxB);
-    scale_a = ldexpf(1.f, s_a);
-    scale_b = ldexpf(1.f, s_b);
-    unscale = ldexpf(1.f, -(s_a + s_b));
-  }
+  float scale_a, scale_b, unscale;
+  renorm_begin<PREC>(rn, amaxA, amaxB, scale_a, scale_b, unscale);
 
   f4 acc[4][8];
 #pragma unroll
@@ -440,6 +488,7 @@ cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const fl
     __syncthreads();
   }
 
+  float mx = 0.f;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -454,13 +503,18 @@ cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const fl
       else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
       C[row * N + col] = o0;
       C[(row + 1) * N + col] = o1;
+      mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
     }
+  if (rn.c) record_amax(rn.c, mx);
 }
 
 // Small or thin shapes: one thread per output element, FP32 complex FMA over K.
 __global__ void __launch_bounds__(256)
 cgemm_simt(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
-           float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc) {
+           float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, Renorm rn) {
+  float scale_a, scale_b, unscale;
+  renorm_begin<P_FP32>(rn, nullptr, nullptr, scale_a, scale_b, unscale);
+  float mx = 0.f;
   const int64_t batch = blockIdx.z;
   A += batch * sa;
   B += batch * sb;
@@ -479,8 +533,11 @@ cgemm_simt(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
       ci = fmaf(x.x, y.y, ci);
       ci = fmaf(x.y, y.x, ci);
     }
-    C[m * N + n] = make_float2(cr, ci);
+    const float2 o = make_float2(cr * unscale, ci * unscale);
+    C[m * N + n] = o;
+    mx = fmaxf(mx, cmax(o));
   }
+  if (rn.c) record_amax(rn.c, mx);
 }
 
 // Large shapes, split-BF16 on operands already split in HBM (hi and lo planes of bfloat16
@@ -530,7 +587,7 @@ __device__ __forceinline__ void v3_issue(char* stage, const uint32_t* __restrict
 __global__ void __launch_bounds__(kV3Threads)
 cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
                   const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl, float2* __restrict__ C,
-                  int64_t sa, int64_t sb, int64_t sc) {
+                  int64_t sa, int64_t sb, int64_t sc, Renorm rn) {
   __shared__ __attribute__((aligned(1024))) char lds[kV3Stages * kV3Stage];
 
   const int64_t tiles_m = M / kV3BM, tiles_n = N / kV3BN;
@@ -603,11 +660,15 @@ cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
     }
   }
 
+  // renormalisation is read only now, so that nothing else is in flight during the load ring
+  float scale_a, scale_b, unscale;
+  renorm_begin<P_BF16X3>(rn, nullptr, nullptr, scale_a, scale_b, unscale);
+  float mx = 0.f;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const f4 v = acc[i][j];
+      const f4 v = acc[i][j] * unscale;
       const float s0 = q ? v[0] : v[2], s1 = q ? v[1] : v[3];
       const float r0 = __shfl_xor(s0, 1), r1 = __shfl_xor(s1, 1);
       const int64_t row = tm * kV3BM + wr + 16 * i + 4 * lg + (q ? 2 : 0);
@@ -617,7 +678,9 @@ cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
       else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
       C[row * N + col] = o0;
       C[(row + 1) * N + col] = o1;
+      mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
     }
+  if (rn.c) record_amax(rn.c, mx);
 }
 
 bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K) {
@@ -628,14 +691,15 @@ bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K) {
 // A, B: split operands, each a hi plane followed by a lo plane (rows x K bfloat16 pairs each),
 // batch strides in complex elements of one plane-pair (= rows * K).
 hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
-                                 float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc) {
+                                 float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc, const Renorm& rn) {
   if (!cgemm_presplit_fits(M, N, K)) return hipErrorInvalidValue;
+  if (rn.c) hipLaunchKernelGGL(renorm_reset, dim3(1), dim3(64), 0, st, rn.c);
   const uint32_t* a = reinterpret_cast<const uint32_t*>(A);
   const uint32_t* b = reinterpret_cast<const uint32_t*>(B);
   const int64_t tiles = (M / kV3BM) * (N / kV3BN);
   // a batch element's region holds its hi plane then its lo plane: 2 * rows * K words
   hipLaunchKernelGGL(cgemm_v3_presplit, dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kV3Threads), 0, st, M, N, K,
-                     a, a + M * K, b, b + N * K, C, 2 * sa, 2 * sb, sc);
+                     a, a + M * K, b, b + N * K, C, 2 * sa, 2 * sb, sc, rn);
   return hipGetLastError();
 }
 
@@ -646,8 +710,11 @@ constexpr int kSkinnyMaxB = 4096;  // complex elements of B held in LDS
 
 __global__ void __launch_bounds__(256)
 cgemm_skinny(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
-             float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc) {
+             float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, Renorm rn) {
   __shared__ float2 Bs[kSkinnyMaxB];
+  float scale_a, scale_b, unscale;
+  renorm_begin<P_FP32>(rn, nullptr, nullptr, scale_a, scale_b, unscale);
+  float mx = 0.f;
   const int64_t batch = blockIdx.z;
   A += batch * sa;
   B += batch * sb;
@@ -673,18 +740,27 @@ cgemm_skinny(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, cons
         ci[t] = fmaf(x.y, y.x, ci[t]);
       }
     }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      cr[t] *= unscale;
+      ci[t] *= unscale;
+      mx = fmaxf(mx, fmaxf(fabsf(cr[t]), fabsf(ci[t])));
+    }
     float4* out = reinterpret_cast<float4*>(C + m * N + 4 * g);
     out[0] = make_float4(cr[0], ci[0], cr[1], ci[1]);
     out[1] = make_float4(cr[2], ci[2], cr[3], ci[3]);
   }
+  if (rn.c) record_amax(rn.c, mx);
 }
 
 // Few outputs, long K (e.g. the last contraction of two halves into a scalar): one workgroup
 // per output element, threads stride over K, then a workgroup reduction.
 __global__ void __launch_bounds__(256)
 cgemm_splitk(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
-             float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc) {
+             float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, Renorm rn) {
   __shared__ float red[2][4];
+  float scale_a, scale_b, unscale;
+  renorm_begin<P_FP32>(rn, nullptr, nullptr, scale_a, scale_b, unscale);
   const int64_t batch = blockIdx.z;
   const int64_t out = blockIdx.x;  // m * N + n
   const int64_t m = out / N, n = out - m * N;
@@ -706,20 +782,21 @@ cgemm_splitk(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, cons
   if ((threadIdx.x & 63) == 0) { red[0][w] = cr; red[1][w] = ci; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const float r = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    const float i = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const float r = (red[0][0] + red[0][1] + red[0][2] + red[0][3]) * unscale;
+    const float i = (red[1][0] + red[1][1] + red[1][2] + red[1][3]) * unscale;
     C[batch * sc + out] = make_float2(r, i);
+    if (rn.c) atomicMax(&rn.c->amax, __float_as_uint(fmaxf(fabsf(r), fabsf(i))));
   }
 }
 
 template <int PREC, int WTM, int WTN>
 static hipError_t launch_tiled(hipStream_t st, int64_t M, int64_t N, int64_t K, const float2* A,
                                const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb,
-                               int64_t sc, const uint32_t* amaxA, const uint32_t* amaxB) {
+                               int64_t sc, const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn) {
   constexpr int BM = 32 * WTM, BN = 16 * WTN;
   const int64_t tiles = (M / BM) * (N / BN);
   hipLaunchKernelGGL((cgemm_mfma<PREC, WTM, WTN>), dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kThreads), 0, st,
-                     M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB);
+                     M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB, rn);
   return hipGetLastError();
 }
 
@@ -736,58 +813,61 @@ static bool use_v2() {
 template <int PREC>
 static hipError_t dispatch(hipStream_t st, int64_t M, int64_t N, int64_t K, const float2* A, const float2* B,
                            float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
-                           const uint32_t* amaxA, const uint32_t* amaxB) {
+                           const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn) {
   if constexpr (PREC != P_FP32) {
     if (use_v2() && M >= kV2BM && N >= kV2BN && K >= kV2BK) {
       const int64_t tiles = (M / kV2BM) * (N / kV2BN);
       hipLaunchKernelGGL((cgemm_v2<PREC>), dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kV2Threads), 0, st,
-                         M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB);
+                         M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB, rn);
       return hipGetLastError();
     }
   }
   if (K < kBK) return hipErrorInvalidValue;
-  if (M >= 128 && N >= 64) return launch_tiled<PREC, 4, 4>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
-  if (M >= 64 && N >= 32) return launch_tiled<PREC, 2, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
-  return launch_tiled<PREC, 1, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
+  if (M >= 128 && N >= 64) return launch_tiled<PREC, 4, 4>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+  if (M >= 64 && N >= 32) return launch_tiled<PREC, 2, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+  return launch_tiled<PREC, 1, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
 }
 
 static bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
                            const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
-                           const uint32_t* amaxA, const uint32_t* amaxB) {
+                           const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn) {
+  if (rn.c && (!rn.a || !rn.b)) return hipErrorInvalidValue;
+  if (rn.c) hipLaunchKernelGGL(renorm_reset, dim3(1), dim3(64), 0, st, rn.c);
   const bool p2 = pow2(M) && pow2(N) && pow2(K);
   const bool big = p2 && precision != P_FP32 && use_v2() && M >= kV2BM && N >= kV2BN && K >= kV2BK;
   const bool tiled = big || (p2 && M >= 32 && N >= 32 && K >= kBK);
   if (!tiled && N >= 4 && N * K <= kSkinnyMaxB && K <= 64 && (N & 3) == 0) {
     const int64_t total = M * (N / 4);
     unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(cgemm_skinny, dim3(blocks, 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C, sa, sb, sc);
+    hipLaunchKernelGGL(cgemm_skinny, dim3(blocks, 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C, sa, sb, sc,
+                       rn);
     return hipGetLastError();
   }
   if (!tiled && M * N <= 4096 && K >= 256) {
     hipLaunchKernelGGL(cgemm_splitk, dim3((unsigned)(M * N), 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C,
-                       sa, sb, sc);
+                       sa, sb, sc, rn);
     return hipGetLastError();
   }
   if (!tiled) {
     const int64_t total = M * N;
     unsigned blocks = (unsigned)((total + 255) / 256);
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(cgemm_simt, dim3(blocks, 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C, sa, sb, sc);
+    hipLaunchKernelGGL(cgemm_simt, dim3(blocks, 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C, sa, sb, sc, rn);
     return hipGetLastError();
   }
   switch (precision) {
-    case P_FP32: return dispatch<P_FP32>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
-    case P_BF16X3: return dispatch<P_BF16X3>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
-    case P_FP16: return dispatch<P_FP16>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB);
+    case P_FP32: return dispatch<P_FP32>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+    case P_BF16X3: return dispatch<P_BF16X3>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+    case P_FP16: return dispatch<P_FP16>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_cgemm(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
                         const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc) {
-  return launch_cgemm_ex(st, precision, M, N, K, A, B, C, batch, sa, sb, sc, nullptr, nullptr);
+  return launch_cgemm_ex(st, precision, M, N, K, A, B, C, batch, sa, sb, sc, nullptr, nullptr, Renorm{});
 }
 
 // Max |re|, |im| of a complex64 array into *amax (as float bits; non-negative floats order

@@ -5,6 +5,24 @@
 
 namespace qf {
 
+// Power-of-two renormalisation state of one stored tensor: its true values are the stored values
+// times 2^e; amax is the largest |re| or |im| among the stored values (float bits, which order
+// like the values since they are non-negative).
+struct NodeScale {
+  int32_t e;
+  uint32_t amax;
+};
+
+// Renormalised GEMM (all three null: off).  With e_A, e_B the binary exponents of the operands'
+// amax (amax = f 2^e, f in [0.5, 1)), the GEMM stores C * 2^-(e_A + e_B), writes
+// c->e = a->e + b->e + e_A + e_B from one thread, and raises c->amax to the stored result's
+// largest magnitude (c->amax is cleared by the launcher first).
+struct Renorm {
+  const NodeScale* a = nullptr;
+  const NodeScale* b = nullptr;
+  NodeScale* c = nullptr;
+};
+
 // One instruction of a qubit's world-line program.
 struct WlInstr {
   int32_t kind;   // 1: one-qubit gate; 2: bond from the q0 side of a diagonal gate (projector);
@@ -80,22 +98,31 @@ hipError_t launch_chain_setup(hipStream_t st, const int64_t* chain0, int G, int 
                               int64_t* base_table, int32_t* chain_b);
 // out[chain_b[g]][j] += root[g][sum_t bit_t(j) << pos[t]] for g = 0..G-1 in order (FP64).
 hipError_t launch_slice_accumulate_batched(hipStream_t st, const float2* root, int k, const int* pos, int G,
-                                           const int32_t* chain_b, double2* out);
+                                           const int32_t* chain_b, double2* out,
+                                           const NodeScale* root_scale = nullptr);
 // *chain0 = value (add = 0) or *chain0 += value (add = 1), as a kernel (graph-capturable).
 hipError_t launch_chain_counter(hipStream_t st, int64_t* chain0, int64_t value, int add);
 
 // Split-BF16 GEMM on operands split by the permute (hi plane then lo plane per batch element).
 bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K);
 hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
-                                 float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc);
+                                 float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
+                                 const Renorm& rn = Renorm{});
 
 // Batched complex GEMM, C[m][n] = sum_k A[m][k] B[n][k].
 hipError_t launch_cgemm(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K,
                         const float2* A, const float2* B, float2* C, int64_t batch, int64_t sa,
                         int64_t sb, int64_t sc);
+// Same, with optional operand max magnitudes for FP16 scaling (ignored when rn is on: then the
+// FP16 operands are scaled from rn.a / rn.b) and optional renormalisation.
+hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
+                           const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
+                           const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn = Renorm{});
+// *amax = max |re|, |im| of x[0..n) (float bits).
+hipError_t launch_amax(hipStream_t st, const float2* x, int64_t n, uint32_t* amax);
 
 // out[j] += root[sum_t bit_t(j) << pos[t]] in complex128, j < 2^k.
 hipError_t launch_slice_accumulate(hipStream_t st, const float2* root, int k, const int* pos,
-                                   double2* out);
+                                   double2* out, const NodeScale* root_scale = nullptr);
 
 } // namespace qf

@@ -28,13 +28,6 @@
 #include "../../include/qfmi.h"
 #include "qf_kernels.h"
 
-namespace qf {
-hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
-                           const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
-                           const uint32_t* amaxA, const uint32_t* amaxB);
-hipError_t launch_amax(hipStream_t st, const float2* x, int64_t n, uint32_t* amax);
-}  // namespace qf
-
 using namespace qf;
 
 static const size_t kCtxScratch = 4096;  // start of the workspace reserved for small slots
@@ -149,6 +142,10 @@ struct qf_plan {
   size_t off_envwl = 0, off_bq = 0, off_bp = 0, off_bea = 0, off_beb = 0;
   std::vector<float2> gates_host;
   int64_t built_version = -1;
+  // power-of-two renormalisation: one NodeScale per node (leaves, then step results)
+  bool renorm = false;
+  size_t off_scales = 0;
+  std::vector<NodeScale> scale_init;
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -297,6 +294,7 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   if (p->G > 1 && p->backward) return fail(ctx, QF_ERR_UNSUPPORTED, "backward plans run chains one at a time");
   if (p->G > 1) p->flags |= QF_PLAN_NO_HOIST;
   p->graph = p->G > 1 && (d->flags & QF_PLAN_GRAPH);
+  p->renorm = !p->backward && !(d->flags & QF_PLAN_NO_RENORM);
 
   // ---- bonds: one bit per diagonal two-qubit gate, time order (ops are sorted by cycle)
   std::vector<std::vector<int>> edge_gate_bits;  // per edge: op indices
@@ -570,6 +568,7 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     if (st.A.permute) trans.push_back({align_up(G * (sizeof(float2) << st.A.nbits)), i, i, &st.A.buf});
     if (st.B.permute) trans.push_back({align_up(G * (sizeof(float2) << st.B.nbits)), i, i, &st.B.buf});
   }
+  if (p->renorm) pers.push_back({align_up((n + S) * sizeof(NodeScale)), 0, S, &p->off_scales});
   if (p->G > 1) {
     pers.push_back({align_up(n * sizeof(LeafDesc)), 0, S, &p->off_leafdesc});
     pers.push_back({align_up((size_t)p->G * n * sizeof(int64_t)), 0, S, &p->off_btable});
@@ -620,6 +619,11 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   }
   p->arena_end = tend;
   p->gates_host.resize(circ->ops.size() * 4);
+  if (p->renorm) {
+    // world-line entries are products of unitary gate entries and projectors: |x| <= 1
+    p->scale_init.assign(n + S, NodeScale{0, 0u});
+    for (int q = 0; q < n; ++q) p->scale_init[q].amax = 0x3f800000u;  // 1.0f
+  }
   *out = p.release();
   return QF_OK;
 }
@@ -715,6 +719,9 @@ static qf_status build_worldlines(qf_plan* p) {
   if (p->G > 1)
     QF_HIP(c, hipMemcpyAsync(c->ws + p->off_leafdesc, p->leaf_desc.data(), p->leaf_desc.size() * sizeof(LeafDesc),
                              hipMemcpyHostToDevice, c->stream));
+  if (p->renorm)
+    QF_HIP(c, hipMemcpyAsync(c->ws + p->off_scales, p->scale_init.data(), p->scale_init.size() * sizeof(NodeScale),
+                             hipMemcpyHostToDevice, c->stream));
   QF_HIP(c, launch_worldlines(c->stream, reinterpret_cast<const WlQubit*>(c->ws + p->off_wlq), p->n, p->max_nbond,
                               reinterpret_cast<const WlInstr*>(c->ws + p->off_prog),
                               reinterpret_cast<const float2*>(c->ws + p->off_gates), wsp(c, p->off_wl)));
@@ -770,19 +777,39 @@ static qf_status run_operand(qf_plan* p, const Operand& op, const uint8_t* bits_
   return QF_OK;
 }
 
-// One GEMM of the plan's precision (FP16 takes the operands' max magnitudes first).
+static NodeScale* node_scale(qf_plan* p, int node) {
+  return reinterpret_cast<NodeScale*>(p->ctx->ws + p->off_scales) + node;
+}
+
+// Renormalisation slots of step i's operands and result (all null when the plan stores true scales).
+static Renorm step_renorm(qf_plan* p, size_t i) {
+  Renorm r;
+  if (!p->renorm) return r;
+  const Step& st = p->steps[i];
+  r.a = node_scale(p, st.A.node);
+  r.b = node_scale(p, st.B.node);
+  r.c = node_scale(p, p->n + (int)i);
+  return r;
+}
+
+static const NodeScale* root_scale(qf_plan* p) {
+  return p->renorm ? node_scale(p, (int)p->nodes.size() - 1) : nullptr;
+}
+
+// One GEMM of the plan's precision (FP16 without renormalisation takes the operands' max
+// magnitudes first).
 static qf_status plan_gemm(qf_plan* p, int64_t M, int64_t N, int64_t K, const float2* A, const float2* B, float2* C,
-                           int64_t batch = 1) {
+                           int64_t batch = 1, const Renorm& rn = Renorm{}) {
   qf_ctx* c = p->ctx;
   const uint32_t *amA = nullptr, *amB = nullptr;
-  if (p->precision == QF_FP16) {
+  if (p->precision == QF_FP16 && !rn.c) {
     uint32_t* slots = reinterpret_cast<uint32_t*>(c->ws);  // context scratch: 2 slots
     QF_HIP(c, launch_amax(c->stream, A, batch * M * K, slots));
     QF_HIP(c, launch_amax(c->stream, B, batch * N * K, slots + 1));
     amA = slots;
     amB = slots + 1;
   }
-  QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, batch, M * K, N * K, M * N, amA, amB));
+  QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, batch, M * K, N * K, M * N, amA, amB, rn));
   return QF_OK;
 }
 
@@ -837,10 +864,11 @@ static qf_status run_step(qf_plan* p, size_t i, const uint8_t* row, int64_t s) {
     e1 = take_event(c);
     if (e0 && e1) QF_HIP(c, hipEventRecord(e0, c->stream));
   }
+  const Renorm rn = step_renorm(p, i);
   if (st.presplit) {
-    QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, 1, M * K, N * K, M * N));
+    QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, 1, M * K, N * K, M * N, rn));
   } else {
-    e = plan_gemm(p, M, N, K, A, B, C);
+    e = plan_gemm(p, M, N, K, A, B, C, 1, rn);
     if (e != QF_OK) return e;
   }
   if (timed && e0 && e1) {
@@ -924,10 +952,11 @@ static qf_status enqueue_group(qf_plan* p, const uint8_t* bits_dev, int64_t s_be
       e1 = take_event(c);
       if (e0 && e1) QF_HIP(c, hipEventRecord(e0, c->stream));
     }
+    const Renorm rn = step_renorm(p, i);
     if (st.presplit) {
-      QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, G, M * K, N * K, M * N));
+      QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, G, M * K, N * K, M * N, rn));
     } else {
-      e = plan_gemm(p, M, N, K, A, B, C, G);
+      e = plan_gemm(p, M, N, K, A, B, C, G, rn);
       if (e != QF_OK) return e;
     }
     if (timed && e0 && e1) {
@@ -938,7 +967,7 @@ static qf_status enqueue_group(qf_plan* p, const uint8_t* bits_dev, int64_t s_be
     }
   }
   QF_HIP(c, launch_slice_accumulate_batched(c->stream, wsp(c, p->nodes.back().offset), k, p->root_pos.data(), G,
-                                            chain_b, reinterpret_cast<double2*>(out_dev)));
+                                            chain_b, reinterpret_cast<double2*>(out_dev), root_scale(p)));
   QF_HIP(c, launch_chain_counter(c->stream, chain0, G, 1));
   return QF_OK;
 }
@@ -1031,7 +1060,7 @@ extern "C" qf_status qf_amplitudes(qf_plan* p, int n_batch, const uint8_t* bits_
       }
       const Node& root = p->nodes.back();
       QF_HIP(c, launch_slice_accumulate(c->stream, wsp(c, root.offset), k, p->root_pos.data(),
-                                        reinterpret_cast<double2*>(out_dev) + ((int64_t)b << k)));
+                                        reinterpret_cast<double2*>(out_dev) + ((int64_t)b << k), root_scale(p)));
       ++done;
     }
   }

@@ -64,28 +64,30 @@ struct AccArgs {
 };
 
 __global__ void __launch_bounds__(256)
-slice_accumulate_kernel(const float2* __restrict__ root, AccArgs a, double2* __restrict__ out) {
+slice_accumulate_kernel(const float2* __restrict__ root, AccArgs a, double2* __restrict__ out,
+                        const NodeScale* __restrict__ root_scale) {
   const int64_t n = (int64_t)1 << a.k;
+  const double f = root_scale ? ldexp(1.0, root_scale->e) : 1.0;  // exact power of two
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     int64_t src = 0;
     for (int t = 0; t < a.k; ++t) src |= ((j >> t) & 1) << a.pos[t];
     const float2 v = root[src];
     double2 o = out[j];
-    o.x += (double)v.x;
-    o.y += (double)v.y;
+    o.x += (double)v.x * f;
+    o.y += (double)v.y * f;
     out[j] = o;
   }
 }
 
 hipError_t launch_slice_accumulate(hipStream_t st, const float2* root, int k, const int* pos,
-                                   double2* out) {
+                                   double2* out, const NodeScale* root_scale) {
   AccArgs a;
   a.k = k;
   for (int t = 0; t < 32; ++t) a.pos[t] = t < k ? pos[t] : 0;
   const int64_t n = (int64_t)1 << k;
   unsigned blocks = (unsigned)((n + 255) / 256);
   if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(slice_accumulate_kernel, dim3(blocks), dim3(256), 0, st, root, a, out);
+  hipLaunchKernelGGL(slice_accumulate_kernel, dim3(blocks), dim3(256), 0, st, root, a, out, root_scale);
   return hipGetLastError();
 }
 
@@ -274,8 +276,9 @@ hipError_t launch_chain_setup(hipStream_t st, const int64_t* chain0, int G, int 
 
 __global__ void __launch_bounds__(256)
 slice_accumulate_batched_kernel(const float2* __restrict__ root, AccArgs a, int G, const int32_t* __restrict__ chain_b,
-                                double2* __restrict__ out) {
+                                double2* __restrict__ out, const NodeScale* __restrict__ root_scale) {
   const int64_t n = (int64_t)1 << a.k;
+  const double f = root_scale ? ldexp(1.0, root_scale->e) : 1.0;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     int64_t src = 0;
     for (int t = 0; t < a.k; ++t) src |= ((j >> t) & 1) << a.pos[t];
@@ -284,22 +287,23 @@ slice_accumulate_batched_kernel(const float2* __restrict__ root, AccArgs a, int 
       if (b < 0) continue;
       const float2 v = root[(int64_t)g * n + src];
       double2 o = out[((int64_t)b << a.k) + j];
-      o.x += (double)v.x;
-      o.y += (double)v.y;
+      o.x += (double)v.x * f;
+      o.y += (double)v.y * f;
       out[((int64_t)b << a.k) + j] = o;
     }
   }
 }
 
 hipError_t launch_slice_accumulate_batched(hipStream_t st, const float2* root, int k, const int* pos, int G,
-                                           const int32_t* chain_b, double2* out) {
+                                           const int32_t* chain_b, double2* out, const NodeScale* root_scale) {
   AccArgs a;
   a.k = k;
   for (int t = 0; t < 32; ++t) a.pos[t] = t < k ? pos[t] : 0;
   const int64_t n = (int64_t)1 << k;
   unsigned blocks = (unsigned)((n + 255) / 256);
   if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(slice_accumulate_batched_kernel, dim3(blocks), dim3(256), 0, st, root, a, G, chain_b, out);
+  hipLaunchKernelGGL(slice_accumulate_batched_kernel, dim3(blocks), dim3(256), 0, st, root, a, G, chain_b, out,
+                     root_scale);
   return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@ from oracle import sv, tn
 from oracle.metrics import rel_err
 from workloads.bitstrings import random_bitstrings, all_bitstrings
 from workloads.circuits import generate, identity_cz, mirror
-from workloads.plans import sweep_plan, region_plan, plan_7x7, nonvanishing_slices
+from workloads.plans import sweep_plan, region_plan, plan_7x7, plan_11x11, nonvanishing_slices
 
 pytestmark = pytest.mark.gpu
 
@@ -29,11 +29,11 @@ def ctx():
     return Context(0)
 
 
-def _amps(ctx, circ, plan, bits, precision="fp32", s_begin=0, s_end=None, hoist=True):
+def _amps(ctx, circ, plan, bits, precision="fp32", s_begin=0, s_end=None, hoist=True, renorm=True):
     import torch
     from paper_1905_00444_amd import Circuit, Plan
     c = Circuit(ctx, circ.to_text())
-    p = Plan(ctx, c, plan, precision, hoist=hoist)
+    p = Plan(ctx, c, plan, precision, hoist=hoist, renorm=renorm)
     out = p.amplitudes(bits, s_begin, s_end)
     torch.cuda.synchronize()
     return out.cpu().numpy()
@@ -226,3 +226,39 @@ def test_7x7_d32_random_slice_vs_tensor_network_oracle(ctx):
     for prec, bound in (("fp32", 1e-5), ("bf16x3", 1e-4)):
         got = _amps(ctx, c, plan, bits, prec, s, s + 1)
         assert rel_err(got, ref) <= bound, prec
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_renormalisation_is_exact(ctx, precision):
+    """Power-of-two renormalisation only moves exponents: FP32 and split-BF16 results with and
+    without it are bitwise identical on a workload whose values stay in range."""
+    _say(f"renormalisation exact {precision}")
+    c = generate(4, 5, 32, 2)
+    qid = c.qubit_of()
+    cuts = [[qid[(1, 3)], qid[(2, 3)], 0, 2], [qid[(3, 1)], qid[(3, 2)], 1, 2]]
+    plan, _ = region_plan(c, 2, 2, cuts, [(3, 4), (2, 4)])
+    bits = random_bitstrings(3, 20, 8)
+    a = _amps(ctx, c, plan, bits, precision)
+    b = _amps(ctx, c, plan, bits, precision, renorm=False)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16"])
+def test_11x11_d24_product_circuit_full_shape(ctx, precision):
+    """121 qubits, (1+24+1), every CZ -> identity, one non-vanishing slice of the 64 (peak 2^30):
+    closed form per qubit.  This slice's amplitudes are about 5e-58, below the FP32 and FP16
+    ranges: only the renormalised path can return them."""
+    _say(f"11x11 d24 product circuit {precision}")
+    base = generate(11, 11, 24, 0)
+    plan, pb = plan_11x11(base)
+    assert max(pb.sizes()) == 30
+    c = identity_cz(base)
+    bits = random_bitstrings(1, 121, 1)
+    s = nonvanishing_slices(base, plan, bits[0], 2)[-1]
+    ref = _product_slice_closed_form(c, plan, bits[0], s)
+    assert np.linalg.norm(ref) > 1e-40
+    got = _amps(ctx, c, plan, bits, precision, s, s + 1)[0]
+    assert rel_err(got, ref) <= BOUND[precision]
+    if precision == "fp32":
+        flat = _amps(ctx, c, plan, bits, precision, s, s + 1, renorm=False)[0]
+        assert rel_err(flat, ref) > 0.5  # underflows at true scale

@@ -270,3 +270,19 @@ def plan_8x9(circ: Circuit, depth: int = 24) -> Tuple[dict, PlanBuilder]:
     R = pb.greedy_region(right, (6, 8))
     pb.contract(L, R)
     return pb.plan(), pb
+
+
+C11_OPEN_SITES = ((10, 8), (10, 9), (10, 10))
+
+
+def plan_11x11(circ: Circuit) -> Tuple[dict, PlanBuilder]:
+    """11x11 grid, depth (1+24+1), bond 8: regions split after row 5 and column 5, whole cuts
+    on the corner bonds (4,10)-(5,10) and (10,4)-(10,5): 64 slices (one path per amplitude is
+    the paper's fidelity 1/64), peak tensor 2^30.  Three output qubits in the bottom-right
+    corner stay open (8 amplitudes per pass)."""
+    qid = circ.qubit_of()
+    cuts = []
+    for a, b in (((4, 10), (5, 10)), ((10, 4), (10, 5))):
+        q0, q1 = sorted((qid[a], qid[b]))
+        cuts.append([q0, q1, 0, 3])
+    return region_plan(circ, 5, 5, cuts, C11_OPEN_SITES)
