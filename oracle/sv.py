@@ -73,3 +73,42 @@ def open_amplitudes(circ, bits: np.ndarray, open_qubits) -> np.ndarray:
             bits[:, q] = (j >> (k - 1 - t)) & 1
         out[:, j] = psi[bit_index(bits)]
     return out
+
+
+def sliced_state(circ, cuts, s: int) -> np.ndarray:
+    """Final state of one path (slice s) of the sliced sum (paper Sec. III-A and III-C), by direct
+    evolution: every cut instance of a diagonal two-qubit gate D on (q0, q1) is replaced by the
+    term of its rank-2 split D = sum_k |k><k|_q0 (x) diag(D[2k], D[2k+1])_q1 that the slice fixes.
+    Cut conventions: bond bit j of an edge is the j-th gate on it in cycle order; slice ids
+    concatenate the cuts' values, first cut most significant, bit bit_lo most significant inside
+    a cut.  Summed over all slices this is final_state(circ) exactly."""
+    if isinstance(circ, str):
+        circ = read_circuit(circ)
+    total = sum(int(c[3]) for c in cuts)
+    fixed = {}
+    off = total
+    for q0, q1, lo, nb in cuts:
+        off -= nb
+        v = (s >> off) & ((1 << nb) - 1)
+        for i in range(nb):
+            fixed[(min(q0, q1), max(q0, q1), lo + i)] = (v >> (nb - 1 - i)) & 1
+    n = circ.n
+    psi = np.zeros(2 ** n, dtype=np.complex128)
+    psi[0] = 1.0
+    seen = {}
+    for (_, _, qs), val in zip(circ.ops, circ.values):
+        if len(qs) == 2:
+            edge = (min(qs), max(qs))
+            j = seen.get(edge, 0)
+            seen[edge] = j + 1
+            if edge + (j,) in fixed:
+                k = fixed[edge + (j,)]
+                # the projector sits on the lower-numbered qubit of the edge
+                term = np.zeros(4, dtype=np.complex128)
+                if qs[0] == edge[0]:
+                    term[2 * k: 2 * k + 2] = val[2 * k: 2 * k + 2]
+                else:
+                    term[[k, 2 + k]] = val[[k, 2 + k]]
+                val = term
+        psi = apply_op(psi, n, qs, val)
+    return psi
