@@ -214,6 +214,27 @@ qf_status qf_time_cgemm(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_
 qf_status qf_time_permute(qf_ctx* ctx, const void* src, void* dst, int nbits, const int32_t* perm,
                           int reps, float* ms);
 
+/* Autotuning of the GEMM kernels that a plan launches (the paper's GPU back-end picks its
+ * kernels by shape class, Sec. III-F; here the choice is measured).  For every distinct GEMM
+ * shape among the plan's steps (precision, M, N, K, chains per launch) the kernel variants that
+ * fit the shape are timed with HIP events on pseudo-random operands placed in the plan's own
+ * workspace buffers, and the fastest is installed in the context: every later launch of that
+ * shape on this context uses it.  Steps on the pre-split split-BF16 kernel have a single variant
+ * and are skipped.
+ * cache_path: NULL, or a JSON file.  Entries it already holds for this device are installed
+ * without timing; the file is then rewritten with every shape known to the context (device,
+ * shape, chosen variant, microseconds per candidate).  A missing file is created.
+ * The plan's intermediate buffers are overwritten (the next qf_amplitudes recomputes all of
+ * them; world-line tensors are kept).  Synchronises the context's stream.
+ * Errors: QF_ERR_ARG (null ctx or plan, plan of another context), QF_ERR_WORKSPACE (workspace
+ * smaller than the plan needs), QF_ERR_HIP, QF_ERR_ARG with text if the file cannot be written. */
+qf_status qf_autotune(qf_ctx* ctx, const qf_plan* plan, const char* cache_path);
+
+/* Variant installed for a GEMM shape on this context (0: none, the shape heuristic applies;
+ * 1..7: see qf_autotune's JSON names tiled4x4, tiled2x2, tiled1x2, large, skinny, splitk, simt). */
+qf_status qf_tuned_variant(const qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, int64_t batch,
+                           int* variant);
+
 /* Event timing of the dominant kernel inside qf_amplitudes: total milliseconds and count of
  * the largest-volume GEMM launches since the last reset (measured with HIP events on the
  * context stream when enabled; enabling adds a stream synchronisation per such launch). */

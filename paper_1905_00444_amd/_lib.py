@@ -17,6 +17,7 @@ QF_PLAN_NO_HOIST = 1
 QF_PLAN_BACKWARD = 2
 QF_PLAN_GRAPH = 4
 QF_PLAN_NO_RENORM = 8
+GEMM_VARIANTS = ("auto", "tiled4x4", "tiled2x2", "tiled1x2", "large", "skinny", "splitk", "simt")
 
 STATUS_NAMES = {0: "QF_OK", -1: "QF_ERR_ARG", -2: "QF_ERR_PLAN", -3: "QF_ERR_WORKSPACE", -4: "QF_ERR_HIP",
                 -5: "QF_ERR_UNSUPPORTED", -6: "QF_ERR_INJECTED"}
@@ -73,6 +74,9 @@ EXPORTS = {
     "qf_time_permute": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_int,
                                   C.POINTER(C.c_float)]),
     "qf_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "qf_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_char_p]),
+    "qf_tuned_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
+                                   C.POINTER(C.c_int)]),
     "qf_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                   C.c_int]),
 }

@@ -6,6 +6,7 @@ provides device memory (the workspace, inputs and outputs) and the stream.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from typing import Optional, Sequence
 
 import numpy as np
@@ -314,3 +315,21 @@ def profile_read(ctx: Context, reset: bool = True):
     fl = C.c_double()
     check(ctx.lib.qf_profile_read(ctx.h, C.byref(ms), C.byref(n), C.byref(fl), 1 if reset else 0), ctx.h)
     return ms.value, n.value, fl.value
+
+
+def autotune(plan: "Plan", cache_path: Optional[str] = None) -> None:
+    """Time the GEMM kernel variants for every GEMM shape of `plan` and install the fastest in the
+    plan's context (qf_autotune); cache_path: JSON file read first and rewritten."""
+    ctx = plan.ctx
+    ctx.ensure_workspace(plan.info()["workspace_bytes"])
+    path = None if cache_path is None else os.fsencode(cache_path)
+    with _torch().cuda.stream(ctx.stream):
+        check(ctx.lib.qf_autotune(ctx.h, plan.h, path), ctx.h)
+
+
+def tuned_variant(ctx: Context, precision: str, M: int, N: int, K: int, batch: int = 1) -> str:
+    """Name of the GEMM variant installed for a shape on this context ("auto" if none)."""
+    v = C.c_int()
+    check(ctx.lib.qf_tuned_variant(ctx.h, PRECISIONS[precision], int(M), int(N), int(K), int(batch), C.byref(v)),
+          ctx.h)
+    return _lib.GEMM_VARIANTS[v.value]

@@ -810,59 +810,87 @@ static bool use_v2() {
   return g_gemm_variant == 1;
 }
 
-template <int PREC>
-static hipError_t dispatch(hipStream_t st, int64_t M, int64_t N, int64_t K, const float2* A, const float2* B,
-                           float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
-                           const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn) {
-  if constexpr (PREC != P_FP32) {
-    if (use_v2() && M >= kV2BM && N >= kV2BN && K >= kV2BK) {
-      const int64_t tiles = (M / kV2BM) * (N / kV2BN);
-      hipLaunchKernelGGL((cgemm_v2<PREC>), dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kV2Threads), 0, st,
-                         M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB, rn);
-      return hipGetLastError();
-    }
+static bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+bool cgemm_variant_fits(int precision, int64_t M, int64_t N, int64_t K, int variant) {
+  const bool p2 = pow2(M) && pow2(N) && pow2(K);
+  switch (variant) {
+    case GEMM_TILED_4X4: return p2 && M >= 128 && N >= 64 && K >= kBK;
+    case GEMM_TILED_2X2: return p2 && M >= 64 && N >= 32 && K >= kBK;
+    case GEMM_TILED_1X2: return p2 && M >= 32 && N >= 32 && K >= kBK;
+    case GEMM_LARGE: return p2 && precision != P_FP32 && M >= kV2BM && N >= kV2BN && K >= kV2BK;
+    case GEMM_SKINNY: return N >= 4 && (N & 3) == 0 && N * K <= kSkinnyMaxB && K <= 64;
+    case GEMM_SPLITK: return M * N <= 4096;
+    case GEMM_SIMT: return M >= 1 && N >= 1 && K >= 1;
   }
-  if (K < kBK) return hipErrorInvalidValue;
-  if (M >= 128 && N >= 64) return launch_tiled<PREC, 4, 4>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
-  if (M >= 64 && N >= 32) return launch_tiled<PREC, 2, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
-  return launch_tiled<PREC, 1, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+  return false;
 }
 
-static bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+int cgemm_default_variant(int precision, int64_t M, int64_t N, int64_t K) {
+  if (use_v2() && cgemm_variant_fits(precision, M, N, K, GEMM_LARGE)) return GEMM_LARGE;
+  if (cgemm_variant_fits(precision, M, N, K, GEMM_TILED_1X2)) {
+    if (M >= 128 && N >= 64) return GEMM_TILED_4X4;
+    if (M >= 64 && N >= 32) return GEMM_TILED_2X2;
+    return GEMM_TILED_1X2;
+  }
+  if (cgemm_variant_fits(precision, M, N, K, GEMM_SKINNY)) return GEMM_SKINNY;
+  if (M * N <= 4096 && K >= 256) return GEMM_SPLITK;
+  return GEMM_SIMT;
+}
+
+template <int PREC>
+static hipError_t launch_mfma(hipStream_t st, int variant, int64_t M, int64_t N, int64_t K, const float2* A,
+                              const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
+                              const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn) {
+  switch (variant) {
+    case GEMM_LARGE:
+      if constexpr (PREC != P_FP32) {
+        const int64_t tiles = (M / kV2BM) * (N / kV2BN);
+        hipLaunchKernelGGL((cgemm_v2<PREC>), dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kV2Threads), 0, st,
+                           M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB, rn);
+        return hipGetLastError();
+      }
+      return hipErrorInvalidValue;
+    case GEMM_TILED_4X4: return launch_tiled<PREC, 4, 4>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+    case GEMM_TILED_2X2: return launch_tiled<PREC, 2, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+    case GEMM_TILED_1X2: return launch_tiled<PREC, 1, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
                            const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
-                           const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn) {
+                           const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn, int variant) {
   if (rn.c && (!rn.a || !rn.b)) return hipErrorInvalidValue;
+  if (M < 1 || N < 1 || K < 1 || batch < 1) return hipErrorInvalidValue;
+  if (precision != P_FP32 && precision != P_BF16X3 && precision != P_FP16) return hipErrorInvalidValue;
+  const int v = (variant != GEMM_AUTO && cgemm_variant_fits(precision, M, N, K, variant))
+                    ? variant : cgemm_default_variant(precision, M, N, K);
   if (rn.c) hipLaunchKernelGGL(renorm_reset, dim3(1), dim3(64), 0, st, rn.c);
-  const bool p2 = pow2(M) && pow2(N) && pow2(K);
-  const bool big = p2 && precision != P_FP32 && use_v2() && M >= kV2BM && N >= kV2BN && K >= kV2BK;
-  const bool tiled = big || (p2 && M >= 32 && N >= 32 && K >= kBK);
-  if (!tiled && N >= 4 && N * K <= kSkinnyMaxB && K <= 64 && (N & 3) == 0) {
-    const int64_t total = M * (N / 4);
-    unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(cgemm_skinny, dim3(blocks, 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C, sa, sb, sc,
-                       rn);
-    return hipGetLastError();
-  }
-  if (!tiled && M * N <= 4096 && K >= 256) {
-    hipLaunchKernelGGL(cgemm_splitk, dim3((unsigned)(M * N), 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C,
-                       sa, sb, sc, rn);
-    return hipGetLastError();
-  }
-  if (!tiled) {
-    const int64_t total = M * N;
-    unsigned blocks = (unsigned)((total + 255) / 256);
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(cgemm_simt, dim3(blocks, 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C, sa, sb, sc, rn);
-    return hipGetLastError();
+  switch (v) {
+    case GEMM_SKINNY: {
+      const int64_t total = M * (N / 4);
+      const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+      hipLaunchKernelGGL(cgemm_skinny, dim3(blocks, 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C, sa, sb,
+                         sc, rn);
+      return hipGetLastError();
+    }
+    case GEMM_SPLITK:
+      hipLaunchKernelGGL(cgemm_splitk, dim3((unsigned)(M * N), 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C,
+                         sa, sb, sc, rn);
+      return hipGetLastError();
+    case GEMM_SIMT: {
+      const unsigned blocks = (unsigned)std::min<int64_t>((M * N + 255) / 256, 65536);
+      hipLaunchKernelGGL(cgemm_simt, dim3(blocks, 1, (unsigned)batch), dim3(256), 0, st, M, N, K, A, B, C, sa, sb, sc,
+                         rn);
+      return hipGetLastError();
+    }
   }
   switch (precision) {
-    case P_FP32: return dispatch<P_FP32>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
-    case P_BF16X3: return dispatch<P_BF16X3>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
-    case P_FP16: return dispatch<P_FP16>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+    case P_FP32: return launch_mfma<P_FP32>(st, v, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+    case P_BF16X3: return launch_mfma<P_BF16X3>(st, v, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+    default: return launch_mfma<P_FP16>(st, v, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
   }
-  return hipErrorInvalidValue;
 }
 
 hipError_t launch_cgemm(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,

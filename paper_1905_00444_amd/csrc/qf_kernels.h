@@ -113,11 +113,31 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
 hipError_t launch_cgemm(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K,
                         const float2* A, const float2* B, float2* C, int64_t batch, int64_t sa,
                         int64_t sb, int64_t sc);
+// GEMM kernel variants (GEMM_AUTO: chosen from the shape).
+enum {
+  GEMM_AUTO = 0,
+  GEMM_TILED_4X4 = 1,  // 256 threads, 128 x 64 complex block tile
+  GEMM_TILED_2X2 = 2,  // 64 x 32
+  GEMM_TILED_1X2 = 3,  // 32 x 32
+  GEMM_LARGE = 4,      // 512 threads, 256 x 128, double-buffered LDS (split-BF16 / FP16 only)
+  GEMM_SKINNY = 5,     // B in LDS, SIMT FP32 (N K <= 4096, K <= 64)
+  GEMM_SPLITK = 6,     // one workgroup per output (M N <= 4096), SIMT FP32
+  GEMM_SIMT = 7,       // one thread per output, SIMT FP32
+  GEMM_N_VARIANTS = 8
+};
+bool cgemm_variant_fits(int precision, int64_t M, int64_t N, int64_t K, int variant);
+int cgemm_default_variant(int precision, int64_t M, int64_t N, int64_t K);
+
 // Same, with optional operand max magnitudes for FP16 scaling (ignored when rn is on: then the
-// FP16 operands are scaled from rn.a / rn.b) and optional renormalisation.
+// FP16 operands are scaled from rn.a / rn.b), optional renormalisation, and a kernel variant
+// (one that does not fit the shape falls back to GEMM_AUTO).
 hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
                            const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
-                           const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn = Renorm{});
+                           const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn = Renorm{},
+                           int variant = GEMM_AUTO);
+
+// p[i] = pseudo-random complex values, re and im uniform in [-1, 1) (hash of seed and i).
+hipError_t launch_fill_random(hipStream_t st, float2* p, int64_t n, uint32_t seed);
 // *amax = max |re|, |im| of x[0..n) (float bits).
 hipError_t launch_amax(hipStream_t st, const float2* x, int64_t n, uint32_t* amax);
 

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -48,6 +49,9 @@ struct qf_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used;
   double prof_flops = 0.0;
   int64_t prof_launches = 0;
+  // GEMM variant per shape (precision, M, N, K, batch), installed by qf_autotune
+  std::map<std::array<int64_t, 5>, int> tune;
+  std::map<std::array<int64_t, 5>, std::string> tune_times;  // microseconds per candidate (JSON text)
 };
 
 struct qf_circuit {
@@ -809,7 +813,13 @@ static qf_status plan_gemm(qf_plan* p, int64_t M, int64_t N, int64_t K, const fl
     amA = slots;
     amB = slots + 1;
   }
-  QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, batch, M * K, N * K, M * N, amA, amB, rn));
+  int variant = GEMM_AUTO;
+  if (!c->tune.empty()) {
+    auto it = c->tune.find({(int64_t)p->precision, M, N, K, batch});
+    if (it != c->tune.end()) variant = it->second;
+  }
+  QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, batch, M * K, N * K, M * N, amA, amB, rn,
+                            variant));
   return QF_OK;
 }
 
@@ -1328,3 +1338,211 @@ qf_status qf_profile_read(qf_ctx* c, double* gemm_ms, int64_t* launches, double*
 }
 
 }  // extern "C"
+
+// ---- autotuning ------------------------------------------------------------------------------
+static const char* const kVariantName[GEMM_N_VARIANTS] = {"auto",  "tiled4x4", "tiled2x2", "tiled1x2",
+                                                          "large", "skinny",   "splitk",   "simt"};
+
+static std::string device_tag(int dev) {
+  hipDeviceProp_t pr;
+  if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+  std::string t = std::string(pr.gcnArchName) + " " + pr.name;
+  for (char& ch : t)
+    if (ch == '"' || ch == '\\' || ch == '\n') ch = ' ';
+  return t;
+}
+
+namespace {
+struct TuneEntry {
+  int variant = 0;
+  std::string times;  // JSON object text of microseconds per candidate
+};
+}  // namespace
+
+// Reads our own JSON layout (one entry per line).  Returns the device tag, fills entries.
+static std::string read_tune_file(const char* path, std::map<std::array<int64_t, 5>, TuneEntry>* out) {
+  std::string dev;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return dev;
+  char line[4096];
+  while (std::fgets(line, sizeof line, f)) {
+    const char* d = std::strstr(line, "\"device\": \"");
+    if (d) {
+      d += 11;
+      const char* e = std::strchr(d, '"');
+      if (e) dev.assign(d, e);
+      continue;
+    }
+    const char* q = std::strstr(line, "{\"precision\":");
+    if (!q) continue;
+    int prec = 0;
+    long long M = 0, N = 0, K = 0, B = 0;
+    char name[32] = {0};
+    if (std::sscanf(q, "{\"precision\": %d, \"M\": %lld, \"N\": %lld, \"K\": %lld, \"batch\": %lld, \"variant\": \"%31[^\"]\"",
+                    &prec, &M, &N, &K, &B, name) != 6)
+      continue;
+    int v = -1;
+    for (int i = 1; i < GEMM_N_VARIANTS; ++i)
+      if (std::strcmp(name, kVariantName[i]) == 0) v = i;
+    if (v < 0) continue;
+    TuneEntry te;
+    te.variant = v;
+    const char* u = std::strstr(q, "\"us\": ");
+    if (u) {
+      u += 6;
+      const char* e = std::strchr(u, '}');
+      if (e) te.times.assign(u, e + 1);
+    }
+    (*out)[{(int64_t)prec, (int64_t)M, (int64_t)N, (int64_t)K, (int64_t)B}] = te;
+  }
+  std::fclose(f);
+  return dev;
+}
+
+// Average milliseconds of one GEMM launch of the given variant (a first launch warms up and is
+// used to size the repetitions: about 10 ms of work, 2 to 20 launches).  *ms < 0: not timed.
+static qf_status time_variant(qf_ctx* c, int prec, int variant, int64_t M, int64_t N, int64_t K, int64_t G,
+                              const float2* A, const float2* B, float2* C, float give_up_ms, float* ms) {
+  hipEvent_t e0 = take_event(c), e1 = take_event(c);
+  if (!e0 || !e1) return fail(c, QF_ERR_HIP, "hipEventCreate failed");
+  auto launch = [&]() {
+    return launch_cgemm_ex(c->stream, prec, M, N, K, A, B, C, G, M * K, N * K, M * N, nullptr, nullptr, Renorm{},
+                           variant);
+  };
+  *ms = -1.f;
+  QF_HIP(c, hipEventRecord(e0, c->stream));
+  QF_HIP(c, launch());
+  QF_HIP(c, hipEventRecord(e1, c->stream));
+  QF_HIP(c, hipEventSynchronize(e1));
+  float t1 = 0.f;
+  QF_HIP(c, hipEventElapsedTime(&t1, e0, e1));
+  if (give_up_ms > 0.f && t1 > give_up_ms) {
+    *ms = t1;
+    c->ev_pool.push_back(e0);
+    c->ev_pool.push_back(e1);
+    return QF_OK;
+  }
+  const int reps = std::max(2, std::min(20, (int)std::ceil(10.0 / std::max(1e-3f, t1))));
+  QF_HIP(c, hipEventRecord(e0, c->stream));
+  for (int r = 0; r < reps; ++r) QF_HIP(c, launch());
+  QF_HIP(c, hipEventRecord(e1, c->stream));
+  QF_HIP(c, hipEventSynchronize(e1));
+  float t = 0.f;
+  QF_HIP(c, hipEventElapsedTime(&t, e0, e1));
+  *ms = t / reps;
+  c->ev_pool.push_back(e0);
+  c->ev_pool.push_back(e1);
+  return QF_OK;
+}
+
+// Candidate variants for a shape: every variant that fits, minus those that cannot win
+// (one-thread-per-output SIMT kernels where an MFMA tile fits, small tiles where the 128 x 64
+// tile already yields thousands of workgroups).
+static std::vector<int> tune_candidates(int prec, int64_t M, int64_t N, int64_t K, int64_t G) {
+  std::vector<int> v;
+  const bool mfma = cgemm_variant_fits(prec, M, N, K, GEMM_TILED_1X2);
+  const bool big_grid = cgemm_variant_fits(prec, M, N, K, GEMM_TILED_4X4) && (M / 128) * (N / 64) * G >= 2048;
+  for (int i = 1; i < GEMM_N_VARIANTS; ++i) {
+    if (!cgemm_variant_fits(prec, M, N, K, i)) continue;
+    if (mfma && (i == GEMM_SIMT || i == GEMM_SPLITK)) continue;
+    if (big_grid && (i == GEMM_TILED_2X2 || i == GEMM_TILED_1X2)) continue;
+    v.push_back(i);
+  }
+  const int d = cgemm_default_variant(prec, M, N, K);  // time the default first
+  std::stable_partition(v.begin(), v.end(), [d](int x) { return x == d; });
+  return v;
+}
+
+extern "C" qf_status qf_autotune(qf_ctx* c, const qf_plan* pc, const char* path) {
+  if (!c || !pc || pc->ctx != c) return QF_ERR_ARG;
+  qf_plan* p = const_cast<qf_plan*>(pc);
+  if (!c->ws || c->ws_bytes < p->arena_end)
+    return fail(c, QF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p->arena_end) + " bytes");
+  QF_HIP(c, hipSetDevice(c->device));
+  const std::string dev = device_tag(c->device);
+  std::map<std::array<int64_t, 5>, TuneEntry> file;
+  if (path) {
+    const std::string fdev = read_tune_file(path, &file);
+    if (fdev != dev) file.clear();
+  }
+  std::map<std::array<int64_t, 5>, std::string>& measured = c->tune_times;
+  const int n = p->n;
+  const int64_t G = p->G;
+  uint32_t seed = 1;
+  for (size_t i = 0; i < p->steps.size(); ++i) {
+    const Step& st = p->steps[i];
+    if (st.presplit) continue;
+    const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+    const std::array<int64_t, 5> key = {(int64_t)p->precision, M, N, K, G};
+    auto fit = file.find(key);
+    if (fit != file.end()) {
+      c->tune[key] = fit->second.variant;
+      continue;
+    }
+    if (measured.count(key) && c->tune.count(key)) continue;
+    const Node& na = p->nodes[st.A.node];
+    const Node& nb = p->nodes[st.B.node];
+    if ((na.leaf && !st.A.permute) || (nb.leaf && !st.B.permute)) continue;
+    float2* A = wsp(c, st.A.permute ? st.A.buf : na.offset);
+    float2* B = wsp(c, st.B.permute ? st.B.buf : nb.offset);
+    float2* C = wsp(c, p->nodes[n + i].offset);
+    QF_HIP(c, launch_fill_random(c->stream, A, G * M * K, seed++));
+    QF_HIP(c, launch_fill_random(c->stream, B, G * N * K, seed++));
+    int best = GEMM_AUTO;
+    float best_ms = 0.f;
+    std::string times = "{";
+    for (int v : tune_candidates(p->precision, M, N, K, G)) {
+      float ms = 0.f;
+      qf_status e = time_variant(c, p->precision, v, M, N, K, G, A, B, C, best > 0 ? 3.f * best_ms : 0.f, &ms);
+      if (e != QF_OK) return e;
+      char buf[64];
+      std::snprintf(buf, sizeof buf, "%s\"%s\": %.2f", times.size() > 1 ? ", " : "", kVariantName[v], 1e3 * ms);
+      times += buf;
+      if (best == GEMM_AUTO || ms < best_ms) {
+        best = v;
+        best_ms = ms;
+      }
+    }
+    times += "}";
+    if (best != GEMM_AUTO) {
+      c->tune[key] = best;
+      measured[key] = times;
+    }
+  }
+  QF_HIP(c, hipStreamSynchronize(c->stream));
+  c->last_built = nullptr;  // nothing of the plan's intermediate state survives
+  if (!path) return QF_OK;
+  // rewrite the file: entries of the file (other shapes, same device) plus the context's table
+  for (const auto& kv : c->tune) {
+    TuneEntry te;
+    te.variant = kv.second;
+    auto m = measured.find(kv.first);
+    auto f0 = file.find(kv.first);
+    te.times = m != measured.end() ? m->second : (f0 != file.end() ? f0->second.times : std::string("{}"));
+    file[kv.first] = te;
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return fail(c, QF_ERR_ARG, std::string("cannot write ") + tmp);
+  std::fprintf(f, "{\n  \"device\": \"%s\",\n  \"entries\": [\n", dev.c_str());
+  size_t k = 0;
+  for (const auto& kv : file) {
+    const auto& key = kv.first;
+    std::fprintf(f, "    {\"precision\": %d, \"M\": %lld, \"N\": %lld, \"K\": %lld, \"batch\": %lld, \"variant\": \"%s\", \"us\": %s}%s\n",
+                 (int)key[0], (long long)key[1], (long long)key[2], (long long)key[3], (long long)key[4],
+                 kVariantName[kv.second.variant], kv.second.times.empty() ? "{}" : kv.second.times.c_str(),
+                 ++k < file.size() ? "," : "");
+  }
+  std::fprintf(f, "  ]\n}\n");
+  if (std::fclose(f) != 0 || std::rename(tmp.c_str(), path) != 0)
+    return fail(c, QF_ERR_ARG, std::string("cannot write ") + path);
+  return QF_OK;
+}
+
+extern "C" qf_status qf_tuned_variant(const qf_ctx* c, int precision, int64_t M, int64_t N, int64_t K, int64_t batch,
+                                      int* variant) {
+  if (!c || !variant) return QF_ERR_ARG;
+  auto it = c->tune.find({(int64_t)precision, M, N, K, batch});
+  *variant = it == c->tune.end() ? 0 : it->second;
+  return QF_OK;
+}

@@ -234,6 +234,30 @@ __global__ void __launch_bounds__(256) zero_kernel(uint4* __restrict__ p, int64_
 }
 
 // Clears `bytes` (a multiple of 16, 16-byte aligned) with a kernel, so it may sit in a captured graph.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {  // lowbias32 integer hash
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ void __launch_bounds__(256) fill_random_kernel(float2* __restrict__ p, int64_t n, uint32_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t h0 = mix32((uint32_t)i ^ mix32(seed ^ (uint32_t)(i >> 32)));
+    const uint32_t h1 = mix32(h0 + 0x9e3779b9U);
+    p[i] = make_float2((float)(int32_t)h0 * 0x1p-31f, (float)(int32_t)h1 * 0x1p-31f);
+  }
+}
+
+hipError_t launch_fill_random(hipStream_t st, float2* p, int64_t n, uint32_t seed) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(fill_random_kernel, dim3(blocks), dim3(256), 0, st, p, n, seed);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(hipStream_t st, void* p, size_t bytes) {
   const int64_t n16 = (int64_t)(bytes / 16);
   if (n16 == 0) return hipSuccess;

@@ -153,3 +153,21 @@ def test_workspace_required_before_compute():
     lib.qf_plan_destroy(ph)
     lib.qf_circuit_destroy(ch)
     lib.qf_ctx_destroy(ctx)
+
+
+def test_autotune_argument_checks_without_device():
+    lib, ctx = _host_ctx()
+    c = generate(3, 3, 8, 0)
+    st, ch = _circuit(lib, ctx, c)
+    st, ph = _plan(lib, ctx, ch, sweep_plan(c))
+    assert lib.qf_autotune(None, ph, None) == _lib.QF_ERR_ARG
+    assert lib.qf_autotune(ctx, None, None) == _lib.QF_ERR_ARG
+    # no workspace: refused before any device call
+    assert lib.qf_autotune(ctx, ph, None) == _lib.QF_ERR_WORKSPACE
+    v = C.c_int(-1)
+    assert lib.qf_tuned_variant(ctx, 1, 1 << 15, 1 << 15, 1 << 15, 1, C.byref(v)) == 0
+    assert v.value == 0
+    assert lib.qf_tuned_variant(None, 1, 1, 1, 1, 1, C.byref(v)) == _lib.QF_ERR_ARG
+    lib.qf_plan_destroy(ph)
+    lib.qf_circuit_destroy(ch)
+    lib.qf_ctx_destroy(ctx)

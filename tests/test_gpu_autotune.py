@@ -1,0 +1,59 @@
+"""GEMM autotuning through the C-ABI: the cache file it writes, the variants it installs, and
+that amplitudes computed after tuning (with the plan's buffers overwritten by the timing runs)
+still match the state vector."""
+import json
+
+import numpy as np
+import pytest
+
+from oracle import sv
+from oracle.metrics import rel_err
+from workloads.bitstrings import random_bitstrings
+from workloads.circuits import generate
+from workloads.plans import region_plan
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup():
+    c = generate(4, 5, 32, 2)
+    qid = c.qubit_of()
+    cuts = [[qid[(1, 3)], qid[(2, 3)], 0, 2], [qid[(3, 1)], qid[(3, 2)], 1, 2]]
+    plan, _ = region_plan(c, 2, 2, cuts, [(3, 4), (2, 4)])
+    return c, plan
+
+
+@pytest.mark.parametrize("precision,batch", [("fp32", 1), ("bf16x3", 4)])
+def test_autotune_cache_and_results(tmp_path, precision, batch):
+    import torch
+    from paper_1905_00444_amd import Context, Circuit, Plan, autotune, tuned_variant, _lib
+    print(f"autotune {precision} batch {batch}", flush=True)
+    c, plan = _setup()
+    bits = random_bitstrings(4, 20, 11)
+    ref = sv.open_amplitudes(c.to_text(), bits, plan["open"])
+    ctx = Context(0)
+    p = Plan(ctx, Circuit(ctx, c.to_text()), plan, precision, batch=batch)
+    before = p.amplitudes(bits)
+    torch.cuda.synchronize()
+    path = tmp_path / "tune.json"
+    autotune(p, str(path))
+    doc = json.loads(path.read_text())
+    assert doc["device"] and doc["entries"]
+    for e in doc["entries"]:
+        assert e["variant"] in _lib.GEMM_VARIANTS[1:]
+        assert e["batch"] == batch
+        assert e["variant"] in e["us"] and all(t > 0 for t in e["us"].values())
+        assert tuned_variant(ctx, precision, e["M"], e["N"], e["K"], e["batch"]) == e["variant"]
+    after = p.amplitudes(bits)
+    torch.cuda.synchronize()
+    bound = 1e-5 if precision == "fp32" else 1e-4
+    assert rel_err(before.cpu().numpy(), ref) <= bound
+    assert rel_err(after.cpu().numpy(), ref) <= bound
+    # a fresh context takes every entry from the file without timing; the file keeps its entries
+    ctx2 = Context(0)
+    p2 = Plan(ctx2, Circuit(ctx2, c.to_text()), plan, precision, batch=batch)
+    autotune(p2, str(path))
+    doc2 = json.loads(path.read_text())
+    assert doc2["entries"] == doc["entries"]
+    for e in doc["entries"]:
+        assert tuned_variant(ctx2, precision, e["M"], e["N"], e["K"], e["batch"]) == e["variant"]
