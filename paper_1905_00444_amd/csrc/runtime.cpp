@@ -439,6 +439,7 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   if (d->n_steps != n - 1 || !d->steps) return fail(ctx, QF_ERR_PLAN, "a plan over n tensors needs exactly n-1 steps");
   std::vector<char> used(2 * n, 0);
   p->peak_bits = 0;
+  p->nodes.reserve((size_t)n + d->n_steps);
   for (int i = 0; i < d->n_steps; ++i) {
     const int l = d->steps[2 * i], r = d->steps[2 * i + 1];
     if (l < 0 || r < 0 || l >= n + i || r >= n + i || l == r)
@@ -454,12 +455,13 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     nd.dep_bits = L.dep_bits || R.dep_bits;
     nd.dep_cuts = L.dep_cuts | R.dep_cuts;
     if ((int)nd.labels.size() > 40) return fail(ctx, QF_ERR_UNSUPPORTED, "intermediate tensor above 2^40 elements");
-    p->nodes.push_back(nd);
+    // (L and R refer into p->nodes: use them before the push_back below)
+    p->peak_bits = std::max({p->peak_bits, (int)nd.labels.size(), (int)L.labels.size(), (int)R.labels.size()});
+    p->nodes.push_back(std::move(nd));
     Step st;
     st.l = l;
     st.r = r;
     p->steps.push_back(st);
-    p->peak_bits = std::max({p->peak_bits, (int)nd.labels.size(), (int)L.labels.size(), (int)R.labels.size()});
   }
   const Node& root = p->nodes.back();
   if ((int)root.labels.size() != (int)p->open.size())
