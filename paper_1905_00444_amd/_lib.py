@@ -8,7 +8,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqfmi.so")
+LIB_PATH = os.environ.get("QFMI_LIB") or os.path.join(HERE, "libqfmi.so")  # QFMI_LIB: another build
 
 QF_OK, QF_ERR_ARG, QF_ERR_PLAN, QF_ERR_WORKSPACE, QF_ERR_HIP, QF_ERR_UNSUPPORTED, QF_ERR_INJECTED = 0, -1, -2, -3, -4, -5, -6
 QF_FP32, QF_BF16X3, QF_FP16 = 0, 1, 2
