@@ -223,7 +223,8 @@ def main():
         "flops_per_step": flops_step,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None,
-                     "kernel": "cgemm_mfma<BF16X3> on the 2^15 x 2^15 x 2^15 complex contractions",
+                     "kernel": "cgemm_v3_presplit (split-BF16, operands split by the preceding permute) on the "
+                               "2^15 x 2^15 x 2^15 complex contractions",
                      "peak_note": "2516.6 TFLOP/s dense BF16 MFMA / 3 products per complex FP32 product; "
                                   "achieved counts algorithmic complex flops 8*M*N*K",
                      "launches": bf["gemm_launches"], "avg_ms": gemm_avg_ms},

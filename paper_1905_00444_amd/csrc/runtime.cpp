@@ -529,7 +529,12 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     st.k_bits = (int)K.size();
     st.m_bits = xf;
     st.n_bits = yf;
-    st.presplit = p->precision == QF_BF16X3 && !p->backward &&
+    // QFMI_NO_PRESPLIT=1 keeps the split in the GEMM's LDS staging (comparison runs)
+    static const bool no_presplit = [] {
+      const char* e = std::getenv("QFMI_NO_PRESPLIT");
+      return e && e[0] == '1';
+    }();
+    st.presplit = p->precision == QF_BF16X3 && !p->backward && !no_presplit &&
                   cgemm_presplit_fits((int64_t)1 << xf, (int64_t)1 << yf, (int64_t)1 << K.size());
     if (st.presplit) {
       for (Operand* op : {&st.A, &st.B}) {
