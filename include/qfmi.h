@@ -119,6 +119,9 @@ typedef struct {
   double flops_next_slice;  /* average flops of each later slice of the same bitstring */
   double permute_bytes;     /* bytes read + written by permutes per slice (no reuse) */
   size_t workspace_bytes;   /* workspace the plan needs */
+  double mfma_flops_per_slice; /* matrix-core flops issued per slice with the default kernels:
+                                  3x the algorithmic count for split-BF16 (three products), 1x
+                                  for FP32 and FP16, 0 for steps on the SIMT kernels */
 } qf_plan_info;
 
 typedef struct qf_ctx qf_ctx;

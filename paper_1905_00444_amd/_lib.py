@@ -42,7 +42,8 @@ class qf_plan_info(C.Structure):
     _fields_ = [("n_slices", C.c_int64), ("n_open", C.c_int32), ("n_steps", C.c_int32), ("peak_bits", C.c_int32),
                 ("n_qubits", C.c_int32), ("flops_per_slice", C.c_double), ("flops_hoisted", C.c_double),
                 ("flops_first_slice", C.c_double), ("flops_next_slice", C.c_double),
-                ("permute_bytes", C.c_double), ("workspace_bytes", C.c_size_t)]
+                ("permute_bytes", C.c_double), ("workspace_bytes", C.c_size_t),
+                ("mfma_flops_per_slice", C.c_double)]
 
 
 EXPORTS = {

@@ -696,6 +696,12 @@ qf_status qf_plan_info_get(const qf_plan* p, qf_plan_info* out) {
   out->flops_next_slice = sim > 1 ? (schedule_flops(p, 0, sim, true) - out->flops_first_slice) / (double)(sim - 1) : 0.0;
   out->permute_bytes = p->permute_bytes;
   out->workspace_bytes = p->arena_end;
+  for (const Step& st : p->steps) {
+    const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+    const int v = st.presplit ? GEMM_LARGE : cgemm_default_variant(p->precision, M, N, K);
+    if (v == GEMM_SKINNY || v == GEMM_SPLITK || v == GEMM_SIMT) continue;
+    out->mfma_flops_per_slice += st.flops * (p->precision == QF_BF16X3 ? 3.0 : 1.0);
+  }
   return QF_OK;
 }
 

@@ -82,7 +82,7 @@ def test_plan_info_matches_paper_flop_formula_7x7_d40():
     plan, pb = plan_7x7(c, 40)
     st, ch = _circuit(lib, ctx, c)
     assert st == 0
-    st, ph = _plan(lib, ctx, ch, plan)
+    st, ph = _plan(lib, ctx, ch, plan, precision=_lib.QF_BF16X3)
     assert st == 0, lib.qf_last_error(ctx)
     inf = _lib.qf_plan_info()
     assert lib.qf_plan_info_get(ph, C.byref(inf)) == 0
@@ -93,6 +93,8 @@ def test_plan_info_matches_paper_flop_formula_7x7_d40():
         va, vb = pb.bits_of(pb.members[a]), pb.bits_of(pb.members[b])
         want += 8 * 2.0 ** ((va + vb + vc) / 2)
     assert abs(inf.flops_per_slice - want) / want < 1e-12
+    # split-BF16 issues three MFMA products per complex product; the few SIMT steps issue none
+    assert 2.99 * inf.flops_per_slice < inf.mfma_flops_per_slice <= 3.0 * inf.flops_per_slice
     # the A x B subtree does not depend on the second cut: later slices reuse it
     assert inf.flops_next_slice < inf.flops_first_slice
     f6 = C.c_double()
