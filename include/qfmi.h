@@ -134,6 +134,9 @@ typedef struct qf_plan qf_plan;
 qf_status qf_ctx_create(int device, void* hip_stream, void* workspace, size_t ws_bytes, qf_ctx** out);
 qf_status qf_ctx_set_workspace(qf_ctx* ctx, void* workspace, size_t ws_bytes);
 qf_status qf_ctx_set_stream(qf_ctx* ctx, void* hip_stream);
+/* Destroys the context.  Circuits and plans still alive are detached, not freed: destroy them
+ * as usual later; every other call on them then fails with QF_ERR_ARG.  Destroying a circuit
+ * likewise detaches the plans built on it. */
 void qf_ctx_destroy(qf_ctx* ctx);
 const char* qf_last_error(const qf_ctx* ctx);
 

@@ -23,6 +23,7 @@
 #include <map>
 #include <memory>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -52,6 +53,9 @@ struct qf_ctx {
   // GEMM variant per shape (precision, M, N, K, batch), installed by qf_autotune
   std::map<std::array<int64_t, 5>, int> tune;
   std::map<std::array<int64_t, 5>, std::string> tune_times;  // microseconds per candidate (JSON text)
+  // live objects created on this context (destroying the context detaches them)
+  std::set<qf_circuit*> circuits;
+  std::set<qf_plan*> plans;
 };
 
 struct qf_circuit {
@@ -60,6 +64,7 @@ struct qf_circuit {
   std::vector<qf_op> ops;  // sorted by (cycle, input order)
   std::vector<int> order;  // ops[i] is input op order[i]
   int64_t version = 0;
+  std::set<qf_plan*> plans;  // live plans built on this circuit
 };
 
 namespace {
@@ -199,8 +204,15 @@ qf_status qf_ctx_set_stream(qf_ctx* ctx, void* hip_stream) {
   return QF_OK;
 }
 
+static void plan_release_graph(qf_plan* p);
+
 void qf_ctx_destroy(qf_ctx* ctx) {
   if (!ctx) return;
+  // plans and circuits that outlive their context are detached: every later call on them fails
+  // with QF_ERR_ARG, and destroying them touches nothing of the context
+  for (qf_plan* p : ctx->plans) plan_release_graph(p);
+  for (qf_plan* p : ctx->plans) p->ctx = nullptr;
+  for (qf_circuit* c : ctx->circuits) c->ctx = nullptr;
   for (auto& p : ctx->ev_used) { ctx->ev_pool.push_back(p.first); ctx->ev_pool.push_back(p.second); }
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
@@ -245,6 +257,7 @@ qf_status qf_circuit_create(qf_ctx* ctx, int rows, int cols, const uint8_t* pres
   std::stable_sort(c->order.begin(), c->order.end(), [&](int a, int b) { return ops[a].cycle < ops[b].cycle; });
   c->ops.resize(n_ops);
   for (int i = 0; i < n_ops; ++i) c->ops[i] = ops[c->order[i]];
+  ctx->circuits.insert(c);
   *out = c;
   return QF_OK;
 }
@@ -257,7 +270,12 @@ qf_status qf_circuit_set_values(qf_circuit* circ, const float* values) {
   return QF_OK;
 }
 
-void qf_circuit_destroy(qf_circuit* circ) { delete circ; }
+void qf_circuit_destroy(qf_circuit* circ) {
+  if (!circ) return;
+  for (qf_plan* p : circ->plans) p->circ = nullptr;  // such plans fail with QF_ERR_ARG from now on
+  if (circ->ctx) circ->ctx->circuits.erase(circ);
+  delete circ;
+}
 
 // ---------------------------------------------------------------------------------------------
 static bool contains(const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); }
@@ -282,6 +300,7 @@ static bool is_identity(const std::vector<int>& perm) {
 
 qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, qf_plan** out) {
   if (!ctx || !circ || !d || !out) return fail(ctx, QF_ERR_ARG, "qf_plan_create: null argument");
+  if (circ->ctx != ctx) return fail(ctx, QF_ERR_ARG, "qf_plan_create: the circuit belongs to another context");
   *out = nullptr;
   if (d->precision < QF_FP32 || d->precision > QF_FP16) return fail(ctx, QF_ERR_ARG, "unknown precision");
   const int n = circ->n;
@@ -635,17 +654,30 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     p->scale_init.assign(n + S, NodeScale{0, 0u});
     for (int q = 0; q < n; ++q) p->scale_init[q].amax = 0x3f800000u;  // 1.0f
   }
+  ctx->plans.insert(p.get());
+  circ->plans.insert(p.get());
   *out = p.release();
   return QF_OK;
 }
 
+// Destroys a plan's captured graph after the work queued on its stream has finished.
+static void plan_release_graph(qf_plan* p) {
+  if (!p->gexec) return;
+  if (p->ctx) (void)hipStreamSynchronize(p->ctx->stream);
+  (void)hipGraphExecDestroy(p->gexec);
+  (void)hipGraphDestroy(p->graph_obj);
+  p->gexec = nullptr;
+  p->graph_obj = nullptr;
+}
+
 void qf_plan_destroy(qf_plan* plan) {
-  if (plan && plan->ctx && plan->ctx->last_built == plan) plan->ctx->last_built = nullptr;
-  if (plan && plan->gexec) {
-    (void)hipStreamSynchronize(plan->ctx->stream);
-    (void)hipGraphExecDestroy(plan->gexec);
-    (void)hipGraphDestroy(plan->graph_obj);
+  if (!plan) return;
+  plan_release_graph(plan);
+  if (plan->ctx) {
+    if (plan->ctx->last_built == plan) plan->ctx->last_built = nullptr;
+    plan->ctx->plans.erase(plan);
   }
+  if (plan->circ) plan->circ->plans.erase(plan);
   delete plan;
 }
 
@@ -1046,7 +1078,7 @@ static qf_status amplitudes_batched(qf_plan* p, int n_batch, const uint8_t* bits
 
 extern "C" qf_status qf_amplitudes(qf_plan* p, int n_batch, const uint8_t* bits_dev, int64_t s_begin, int64_t s_end,
                                    double* out_dev) {
-  if (!p) return QF_ERR_ARG;
+  if (!p || !p->ctx || !p->circ) return QF_ERR_ARG;
   qf_ctx* c = p->ctx;
   const int64_t S = (int64_t)1 << p->total_cut_bits;
   if (n_batch < 0 || s_begin < 0 || s_end > S || s_begin > s_end || (n_batch > 0 && (!bits_dev || !out_dev)))
@@ -1125,7 +1157,7 @@ static qf_status route_env(qf_plan* p, const Operand& op, const float2* E, const
 
 extern "C" qf_status qf_backward(qf_plan* p, int n_batch, const uint8_t* bits_dev, const double* cot_dev,
                                  int64_t s_begin, int64_t s_end, float* grad_dev) {
-  if (!p) return QF_ERR_ARG;
+  if (!p || !p->ctx || !p->circ) return QF_ERR_ARG;
   qf_ctx* c = p->ctx;
   const int64_t S = (int64_t)1 << p->total_cut_bits;
   if (n_batch < 0 || s_begin < 0 || s_end > S || s_begin > s_end ||
@@ -1467,7 +1499,7 @@ static std::vector<int> tune_candidates(int prec, int64_t M, int64_t N, int64_t 
 }
 
 extern "C" qf_status qf_autotune(qf_ctx* c, const qf_plan* pc, const char* path) {
-  if (!c || !pc || pc->ctx != c) return QF_ERR_ARG;
+  if (!c || !pc || pc->ctx != c || !pc->circ) return QF_ERR_ARG;
   qf_plan* p = const_cast<qf_plan*>(pc);
   if (!c->ws || c->ws_bytes < p->arena_end)
     return fail(c, QF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p->arena_end) + " bytes");

@@ -173,3 +173,32 @@ def test_autotune_argument_checks_without_device():
     lib.qf_plan_destroy(ph)
     lib.qf_circuit_destroy(ch)
     lib.qf_ctx_destroy(ctx)
+
+
+def test_destroy_order_detaches_instead_of_dangling():
+    """Objects may be released in any order (Python's collector does not order finalisers):
+    destroying a context or a circuit detaches what was built on it."""
+    lib, ctx = _host_ctx()
+    c = generate(3, 3, 8, 0)
+    st, ch = _circuit(lib, ctx, c)
+    st, p1 = _plan(lib, ctx, ch, sweep_plan(c))
+    st, p2 = _plan(lib, ctx, ch, sweep_plan(c))
+    out = C.c_void_p(16)
+    bits = C.c_void_p(16)
+    lib.qf_circuit_destroy(ch)       # p1, p2 lose their circuit
+    assert lib.qf_amplitudes(p1, 1, bits, 0, 1, out) == _lib.QF_ERR_ARG
+    lib.qf_ctx_destroy(ctx)          # and their context
+    assert lib.qf_amplitudes(p2, 1, bits, 0, 1, out) == _lib.QF_ERR_ARG
+    inf = _lib.qf_plan_info()
+    assert lib.qf_plan_info_get(p2, C.byref(inf)) == 0  # host-side description stays readable
+    lib.qf_plan_destroy(p1)
+    lib.qf_plan_destroy(p2)
+    # a circuit of another context is refused
+    lib, ctx_a = _host_ctx()
+    lib, ctx_b = _host_ctx()
+    st, ch = _circuit(lib, ctx_a, c)
+    st, ph = _plan(lib, ctx_b, ch, sweep_plan(c))
+    assert st == _lib.QF_ERR_ARG
+    lib.qf_ctx_destroy(ctx_a)
+    lib.qf_circuit_destroy(ch)
+    lib.qf_ctx_destroy(ctx_b)

@@ -124,17 +124,39 @@ def _product_slice(circ, plan, bits_row, s):
     return np.prod([vecs[q][bits_row[q]] for q in range(circ.n_qubits)])
 
 
+def _clifford_batch(base, plan, n, seed):
+    """Clifford product circuit (CZ -> identity, T -> S) and n bitstrings with nonzero slice-0
+    amplitudes: the larger component of every qubit, then random flips of the qubits whose two
+    components are equal in magnitude (see the 7x7 product test for why split-BF16 needs it)."""
+    from test_gpu_amplitudes import _product_vectors
+    from workloads.circuits import clifford_substitute
+    c = clifford_substitute(identity_cz(base))
+    vecs = _product_vectors(c, plan, 0)
+    first = np.array([int(np.argmax(np.abs(v))) for v in vecs], dtype=np.uint8)
+    cut_q = {q for cut in plan["cuts"] for q in cut[:2]}
+    free = [q for q, v in enumerate(vecs) if q not in cut_q and abs(abs(v[0]) - abs(v[1])) < 1e-12]
+    rng = np.random.default_rng(seed)
+    bits = np.tile(first, (n, 1))
+    for b in range(1, n):
+        bits[b, free] ^= rng.integers(0, 2, len(free)).astype(np.uint8)
+    return c, bits
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_70_qubit_product_circuit_batched_graph(gctx, precision):
     """8x9 minus two corners, (1+24+1), every CZ -> identity: each chain has a closed form.
-    16 bitstrings x slices 0..7 run as 128 chains, 32 per launch, through the captured graph."""
+    16 bitstrings x slices 0..7 run as 128 chains, 32 per launch, through the captured graph.
+    Split-BF16 runs the Clifford variant."""
     import torch
     from paper_1905_00444_amd import Circuit, Plan
     _say(f"70 qubits product circuit {precision}")
     base = generate(8, 9, 24, 0, C5_REMOVED)
     plan, _ = plan_8x9(base)
-    c = identity_cz(base)
-    bits = random_bitstrings(16, 70, 1)
+    if precision == "bf16x3":
+        c, bits = _clifford_batch(base, plan, 16, 1)
+    else:
+        c = identity_cz(base)
+        bits = random_bitstrings(16, 70, 1)
     p = Plan(gctx, Circuit(gctx, c.to_text()), plan, precision, batch=32, graph=True)
     got = p.amplitudes(bits, 0, 8)
     gctx.synchronize()
