@@ -36,6 +36,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <algorithm>
+#include <string>
 #include "qf_kernels.h"
 
 namespace qf {
@@ -584,6 +585,10 @@ __device__ __forceinline__ void v3_issue(char* stage, const uint32_t* __restrict
   }
 }
 
+// Wave tile WI x WJ MFMA tiles (16 WI rows x 8 WJ complex columns); the 8 waves tile the 256 x 128
+// block as (16 / WI) x (16 / WJ).  The B operand (the expanded one) costs 2 VALU operations per
+// dword per wave, so a narrower wave tile in N halves that work at the same MFMA count.
+template <int WI, int WJ>
 __global__ void __launch_bounds__(kV3Threads)
 cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
                   const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl, float2* __restrict__ C,
@@ -609,19 +614,21 @@ cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
   Bl += batch * sb + tn * kV3BN * K;
   C += batch * sc;
 
+  static_assert(WI * WJ == 32 && 16 * WI <= kV3BM && 8 * WJ <= kV3BN, "8 waves cover the block tile");
+  constexpr int NWN = kV3BN / (8 * WJ);  // waves along N
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 64;
-  const int wc = (wave & 1) * 64;
+  const int wr = (wave / NWN) * (16 * WI);
+  const int wc = (wave % NWN) * (8 * WJ);
   const int l16 = lane & 15, lg = lane >> 4, q = l16 & 1;
   const BExpand bx(q);
   // swizzled 16-byte chunk of this lane's operand reads
   const int a_chunk = (lg ^ ((l16 >> 2) & 3)) * 16;
 
-  f4 acc[4][8];
+  f4 acc[WI][WJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WI; ++i)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < WJ; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
 
   const int64_t nk = K / kV3BK;
   v3_issue(lds, Ah, Al, Bh, Bl, K, 0, wave, lane);
@@ -632,15 +639,15 @@ cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
     __builtin_amdgcn_s_barrier();
     if (kt + 2 < nk) v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, K, (kt + 2) * kV3BK, wave, lane);
     const char* st = lds + (kt % kV3Stages) * kV3Stage;
-    u4 ah[4], al[4];
+    u4 ah[WI], al[WI];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < WI; ++i) {
       const char* p = st + (wr + 16 * i + l16) * 64 + a_chunk;
       ah[i] = *reinterpret_cast<const u4*>(p);
       al[i] = *reinterpret_cast<const u4*>(p + kV3PlaneA);
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < WJ; ++j) {
       const int row = wc + 8 * j + (l16 >> 1);
       const char* p = st + 2 * kV3PlaneA + row * 64 + (lg ^ ((row >> 2) & 3)) * 16;
       u4 bh = *reinterpret_cast<const u4*>(p);
@@ -649,13 +656,13 @@ cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
       for (int e = 0; e < 4; ++e) { bh[e] = bx(bh[e]); bl[e] = bx(bl[e]); }
       const bf8 vbh = __builtin_bit_cast(bf8, bh), vbl = __builtin_bit_cast(bf8, bl);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < WI; ++i)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, al[i]), vbh, acc[i][j], 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < WI; ++i)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), vbl, acc[i][j], 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < WI; ++i)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), vbh, acc[i][j], 0, 0, 0);
     }
   }
@@ -665,9 +672,9 @@ cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
   renorm_begin<P_BF16X3>(rn, nullptr, nullptr, scale_a, scale_b, unscale);
   float mx = 0.f;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WI; ++i)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < WJ; ++j) {
       const f4 v = acc[i][j] * unscale;
       const float s0 = q ? v[0] : v[2], s1 = q ? v[1] : v[3];
       const float r0 = __shfl_xor(s0, 1), r1 = __shfl_xor(s1, 1);
@@ -698,8 +705,17 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
   const uint32_t* b = reinterpret_cast<const uint32_t*>(B);
   const int64_t tiles = (M / kV3BM) * (N / kV3BN);
   // a batch element's region holds its hi plane then its lo plane: 2 * rows * K words
-  hipLaunchKernelGGL(cgemm_v3_presplit, dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kV3Threads), 0, st, M, N, K,
-                     a, a + M * K, b, b + N * K, C, 2 * sa, 2 * sb, sc, rn);
+  // QFMI_V3_WAVES=64x64 selects the 64-row x 64-column wave tile (comparison runs)
+  static const bool wide = [] {
+    const char* e = getenv("QFMI_V3_WAVES");
+    return e && std::string(e) == "64x64";
+  }();
+  if (wide)
+    hipLaunchKernelGGL((cgemm_v3_presplit<4, 8>), dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kV3Threads), 0, st,
+                       M, N, K, a, a + M * K, b, b + N * K, C, 2 * sa, 2 * sb, sc, rn);
+  else
+    hipLaunchKernelGGL((cgemm_v3_presplit<8, 4>), dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kV3Threads), 0, st,
+                       M, N, K, a, a + M * K, b, b + N * K, C, 2 * sa, 2 * sb, sc, rn);
   return hipGetLastError();
 }
 
