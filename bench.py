@@ -106,6 +106,27 @@ def cpu_baseline(circ, plan, pb, bits, flops_per_step, n_amp, reps):
             "fp64_gflops": rate / 1e9}
 
 
+PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "cgemm_v3_presplit_7x7_d40.md")
+GEMM_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1905_00444_amd", "csrc", "cgemm.hip")
+
+
+def measured_traffic():
+    """HBM bytes per dispatch of the dominant kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+        src = hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_dispatch: ([0-9.e+]+) ; kernel source cgemm.hip sha256: ([0-9a-f]+)", text)
+    if not m or m.group(2) != src:
+        return None
+    return float(m.group(1))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -222,7 +243,8 @@ def main():
         "rel_err_bf16x3_vs_fp32_same_prefixes": bf_vs_fp,
         "flops_per_step": flops_step,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None,
+                     "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per dispatch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "cgemm_v3_presplit (split-BF16, operands split by the preceding permute) on the "
                                "2^15 x 2^15 x 2^15 complex contractions",
                      "peak_note": "2516.6 TFLOP/s dense BF16 MFMA / 3 products per complex FP32 product; "
