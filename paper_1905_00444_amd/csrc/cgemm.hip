@@ -548,9 +548,9 @@ cgemm_simt(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
 // moves 16 bytes, one instruction fills 1 KiB = 16 rows x 64 bytes of one plane), through a
 // ring of 3 LDS stages: while tile kt is multiplied, tiles kt+1 and kt+2 are in flight.  Each
 // wave waits only for its own loads of tile kt (vmcnt), then one barrier makes every wave's
-// loads visible.  Within each 16-row group the four 16-byte chunks of a row are stored in the
-// order c ^ ((row >> 2) & 3), so the MFMA operand reads of 16 consecutive rows hit 16 distinct
-// bank groups.
+// loads visible.  The four 16-byte chunks of a row are stored in the order c ^ ((row >> 1) & 3):
+// a 16-byte LDS read serves 8 lanes per pass, and the 8 rows (or 4 distinct B rows) that one pass
+// reads then land in 8 distinct 16-byte bank groups.
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 
@@ -566,7 +566,7 @@ __device__ __forceinline__ void v3_issue(char* stage, const uint32_t* __restrict
                                          const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl,
                                          int64_t K, int64_t k0, int wave, int lane) {
   const int r = lane >> 2, pos = lane & 3;
-  const int c = pos ^ ((r >> 2) & 3);
+  const int c = pos ^ ((r >> 1) & 3);
 #pragma unroll
   for (int t = 0; t < kV3LoadsPerWave; ++t) {
     const int q = wave + 8 * t;  // 1 KiB chunk of the stage: 0..31 A (hi 0..15, lo 16..31), 32..47 B
@@ -622,7 +622,7 @@ cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
   const int l16 = lane & 15, lg = lane >> 4, q = l16 & 1;
   const BExpand bx(q);
   // swizzled 16-byte chunk of this lane's operand reads
-  const int a_chunk = (lg ^ ((l16 >> 2) & 3)) * 16;
+  const int a_chunk = (lg ^ ((l16 >> 1) & 3)) * 16;
 
   f4 acc[WI][WJ];
 #pragma unroll
@@ -649,7 +649,7 @@ cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
 #pragma unroll
     for (int j = 0; j < WJ; ++j) {
       const int row = wc + 8 * j + (l16 >> 1);
-      const char* p = st + 2 * kV3PlaneA + row * 64 + (lg ^ ((row >> 2) & 3)) * 16;
+      const char* p = st + 2 * kV3PlaneA + row * 64 + (lg ^ ((row >> 1) & 3)) * 16;
       u4 bh = *reinterpret_cast<const u4*>(p);
       u4 bl = *reinterpret_cast<const u4*>(p + kV3PlaneB);
 #pragma unroll
