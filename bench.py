@@ -35,7 +35,100 @@ def parse():
     ap.add_argument("--no-subcheck", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="launch one plain 1 GiB device copy first (HBM counter calibration)")
+    ap.add_argument("--workload", default="7x7-d40", choices=["7x7-d40", "8x9-d24", "6x6-d24-grad"],
+                    help="7x7-d40: the benchmark line (default); 8x9-d24: 70 qubits, batched chains through a "
+                         "captured graph, beside the searched plan; 6x6-d24-grad: forward and backward of 64 "
+                         "amplitudes")
     return ap.parse_args()
+
+
+def bench_8x9(args):
+    """70 qubits (8x9 minus two corners, 1+24+1, bond 8): 16 bitstrings x 64 of the 256 slices of
+    the two-halves plan as 1024 chains, 16 per launch, replayed from one captured hipGraph; and the
+    whole amplitudes of the same 16 bitstrings with the plan the search finds (no cut at 2^27)."""
+    import torch
+    from paper_1905_00444_amd import Context, Circuit, Plan, planner
+    from workloads.bitstrings import random_bitstrings
+    from workloads.circuits import generate
+    from workloads.plans import plan_8x9, C5_REMOVED
+    circ = generate(8, 9, 24, 0, C5_REMOVED)
+    text = circ.to_text()
+    hand, _ = plan_8x9(circ)
+    bits = random_bitstrings(16, 70, 1)
+    ctx = Context(0, stream=torch.cuda.Stream())
+    cobj = Circuit(ctx, text)
+    rec = {"metric": "70-qubit (8x9 - 2, 1+24+1) amplitudes", "n_gpus": 1, "data": "synthetic, seeded",
+           "dtype": "bf16x3 (FP32 accumulate)"}
+    G, S = 16, 64
+    p = Plan(ctx, cobj, hand, "bf16x3", batch=G, graph=True)
+    with torch.cuda.stream(ctx.stream):
+        bits_t = torch.from_numpy(bits).to(ctx.device)  # one device copy: the captured graph keys on it
+    out = p.amplitudes(bits_t, 0, S)  # captures the graph, warms up
+    ctx.synchronize()
+    with torch.cuda.stream(ctx.stream):
+        out.zero_()
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    p.amplitudes(bits_t, 0, S, out=out)
+    ctx.synchronize()
+    dt = time.perf_counter() - t0
+    chains = 16 * S
+    fl = chains * p.info()["flops_per_slice"]
+    rec["batched_graph"] = {"chains": chains, "chains_per_launch": G, "slices": S, "seconds": dt,
+                            "chains_per_s": chains / dt, "complex_tflops": fl / dt / 1e12,
+                            "plan": "two halves, cuts (0,4)-(0,5) 3 bits, (1,4)-(1,5) 3 bits, (2,4)-(2,5) 2 bits"}
+    del p
+    best = planner.search(text, 27)
+    q = Plan(ctx, cobj, best.plan, "bf16x3")
+    q.amplitudes(bits[:1])
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    full = q.amplitudes(bits)
+    ctx.synchronize()
+    dt = time.perf_counter() - t0
+    f32 = Plan(ctx, cobj, best.plan, "fp32").amplitudes(bits)
+    ctx.synchronize()
+    from numpy.linalg import norm
+    a, b = full.cpu().numpy(), f32.cpu().numpy()
+    rec["searched_plan"] = {"amplitudes": 16, "seconds": dt, "amplitudes_per_s": 16 / dt,
+                            "complex_tflops": 16 * q.info()["flops_per_slice"] / dt / 1e12,
+                            "plan": repr(best), "rel_err_bf16x3_vs_fp32": float(norm(a - b) / norm(b))}
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+def bench_6x6_grad(args):
+    """6x6 (1+24+1), bond 8, 64 bitstrings: forward amplitudes and the gradient of sum |a|^2 with
+    respect to every gate entry (FP32, row sweep, no cuts)."""
+    import torch
+    from paper_1905_00444_amd import Context, Circuit, Plan
+    from workloads.bitstrings import random_bitstrings
+    from workloads.circuits import generate
+    from workloads.plans import sweep_plan
+    circ = generate(6, 6, 24, 0)
+    plan = sweep_plan(circ)
+    bits = random_bitstrings(64, 36, 1)
+    ctx = Context(0)
+    p = Plan(ctx, Circuit(ctx, circ.to_text()), plan, "fp32", backward=True)
+    a = p.amplitudes(bits)
+    g = p.backward(bits, 2 * a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = p.amplitudes(bits)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        g = p.backward(bits, 2 * a)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd, bwd = (t1 - t0) / args.steps, (t2 - t1) / args.steps
+    fl = 64 * p.info()["flops_per_slice"]
+    print(json.dumps({"metric": "6x6 (1+24+1) forward and backward, 64 bitstrings", "n_gpus": 1, "dtype": "fp32",
+                      "forward_s": fwd, "backward_s": bwd, "forward_amplitudes_per_s": 64 / fwd,
+                      "forward_complex_tflops": fl / fwd / 1e12, "backward_over_forward": bwd / fwd,
+                      "gates": int(g.shape[0]), "data": "synthetic, seeded"}), flush=True)
+    return 0
 
 
 def sub_check(ctx):
@@ -133,6 +226,10 @@ def main():
         print(json.dumps({"error": "single-GPU build: only --gpus 1 is supported; slices shard across GPUs "
                                    "with no communication but that path is not built"}))
         return 2
+    if args.workload == "8x9-d24":
+        return bench_8x9(args)
+    if args.workload == "6x6-d24-grad":
+        return bench_6x6_grad(args)
     import torch
     from paper_1905_00444_amd import Context, Circuit, Plan, profile_enable, profile_read
     from workloads.bitstrings import random_bitstrings
