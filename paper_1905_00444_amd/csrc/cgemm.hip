@@ -737,8 +737,10 @@ __device__ __forceinline__ void v4_rows(const char* st, int wr, int l16, int a_c
   }
 }
 
-// DB = false: no double-buffering; each K-tile reads its B fragments after the barrier and then
-// streams A row group by row group (comparison runs).
+// DB = false (the default schedule): no double-buffering; each K-tile reads its B fragments after
+// the barrier and then streams A row group by row group, the compiler overlapping the A reads of
+// one group with the MFMAs of the previous.  DB = true keeps two B fragment sets in registers
+// (256 VGPRs, which leaves the compiler no room to overlap the A reads; slower).
 template <bool DB>
 __global__ void __launch_bounds__(kV3Threads)
 cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
@@ -864,13 +866,15 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
   const uint32_t* b = reinterpret_cast<const uint32_t*>(B);
   const int64_t tiles = (M / kV3BM) * (N / kV3BN);
   // a batch element's region holds its hi plane then its lo plane: 2 * rows * K words
-  // QFMI_V3_WAVES=64x64 / 128x32 select the kernel without register double-buffering (comparison runs)
+  // QFMI_V3_WAVES=64x64 / 128x32 / db select the other schedules (comparison runs); the default
+  // streams A row groups against B fragments read at the start of each K-tile (fastest measured:
+  // 430 vs 423 (128x32), 408 (64x64) and 398 (db) TFLOP/s on 8192^3 and 2^15-cubed)
   static const int variant = [] {
     const char* e = getenv("QFMI_V3_WAVES");
     if (e && std::string(e) == "64x64") return 1;
     if (e && std::string(e) == "128x32") return 2;
-    if (e && std::string(e) == "stream") return 3;
-    return 0;
+    if (e && std::string(e) == "db") return 0;
+    return 3;
   }();
   const dim3 grid((unsigned)tiles, 1, (unsigned)batch);
   if (variant == 1)
