@@ -199,8 +199,9 @@ def cpu_baseline(circ, plan, pb, bits, flops_per_step, n_amp, reps):
             "fp64_gflops": rate / 1e9}
 
 
-PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "cgemm_v3_presplit_7x7_d40.md")
-GEMM_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1905_00444_amd", "csrc", "cgemm.hip")
+PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "cgemm_v4_presplit_7x7_d40.md")
+GEMM_SRC = [os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1905_00444_amd", "csrc", f)
+            for f in ("cgemm_presplit.hip", "cgemm_common.h")]
 
 
 def measured_traffic():
@@ -211,10 +212,11 @@ def measured_traffic():
     import re
     try:
         text = open(PROFILE).read()
-        src = hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()
+        src = hashlib.sha256(b"".join(open(f, "rb").read() for f in GEMM_SRC)).hexdigest()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_dispatch: ([0-9.e+]+) ; kernel source cgemm.hip sha256: ([0-9a-f]+)", text)
+    m = re.search(r"traffic_bytes_per_dispatch: ([0-9.e+]+) ; kernel source cgemm_presplit.hip \+ cgemm_common.h "
+                  r"sha256: ([0-9a-f]+)", text)
     if not m or m.group(2) != src:
         return None
     return float(m.group(1))
@@ -342,7 +344,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(),
                      "traffic_unit": "bytes per dispatch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": "cgemm_v3_presplit (split-BF16, operands split by the preceding permute) on the "
+                     "kernel": "cgemm_v4_presplit (split-BF16, operands split by the preceding permute) on the "
                                "2^15 x 2^15 x 2^15 complex contractions",
                      "peak_note": "2516.6 TFLOP/s dense BF16 MFMA / 3 products per complex FP32 product; "
                                   "achieved counts algorithmic complex flops 8*M*N*K",
