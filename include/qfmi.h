@@ -192,7 +192,10 @@ qf_status qf_permute(qf_ctx* ctx, const void* src, void* dst, int nbits, const i
 /* Complex GEMM ("G" of TTGT, Sec. III-E), batched:
  *   C[b][m][n] = sum_k A[b][m][k] * B[b][n][k]      (no conjugation), complex64,
  * A row-major M x K, B row-major N x K (both K-contiguous), C row-major M x N.
- * Batch strides are in complex elements.  M, N, K >= 1.  precision: qf_precision. */
+ * Batch strides are in complex elements.  M, N, K >= 1.  precision: qf_precision.
+ * Launches whose output tiles cannot fill the GPU split K over more workgroups when the context
+ * workspace, past its first 4 KiB, holds the partial tiles (split x batch x M x N complex64);
+ * the chunks are then summed in a fixed order.  Without such a workspace K is not split. */
 qf_status qf_cgemm(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, const void* A,
                    const void* B, void* C, int64_t batch, int64_t stride_a, int64_t stride_b,
                    int64_t stride_c);

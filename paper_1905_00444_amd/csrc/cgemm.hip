@@ -53,6 +53,54 @@ hipError_t launch_renorm_reset(hipStream_t st, NodeScale* c) {
   return hipGetLastError();
 }
 
+// Split-K launches (gridDim.y > 1): workgroup y contracts K-chunk y of length kc and writes its
+// raw partial tile to P[y][batch][M][N]; cgemm_split_reduce sums the chunks in ascending order
+// (deterministic) and applies the renormalisation.  A partial keeps only the FP16 operand scales
+// (undone here); the renormalisation exponent is applied by the reduction.
+template <int PREC>
+__device__ __forceinline__ void scales_for(const Renorm& rn, const uint32_t* amaxA, const uint32_t* amaxB,
+                                           bool partial, float& scale_a, float& scale_b, float& unscale) {
+  if (!partial) {
+    renorm_begin<PREC>(rn, amaxA, amaxB, scale_a, scale_b, unscale);
+    return;
+  }
+  int s_a = 0, s_b = 0;
+  if constexpr (PREC == P_FP16) {
+    if (rn.c) {
+      s_a = 14 - renorm_exp(rn.a);
+      s_b = 14 - renorm_exp(rn.b);
+    } else {
+      s_a = fp16_shift(amaxA);
+      s_b = fp16_shift(amaxB);
+    }
+  }
+  scale_a = ldexpf(1.f, s_a);
+  scale_b = ldexpf(1.f, s_b);
+  unscale = ldexpf(1.f, -(s_a + s_b));
+}
+
+__global__ void __launch_bounds__(256)
+cgemm_split_reduce(const float2* __restrict__ P, int split, int64_t batch, int64_t MN, int64_t sc,
+                   float2* __restrict__ C, Renorm rn) {
+  float sa_, sb_, unscale;
+  renorm_begin<P_FP32>(rn, nullptr, nullptr, sa_, sb_, unscale);
+  const int64_t total = batch * MN;
+  float mx = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    float re = 0.f, im = 0.f;
+    for (int y = 0; y < split; ++y) {
+      const float2 v = P[(int64_t)y * total + i];
+      re += v.x;
+      im += v.y;
+    }
+    const float2 o = make_float2(re * unscale, im * unscale);
+    const int64_t b = i / MN;
+    C[b * sc + (i - b * MN)] = o;
+    mx = fmaxf(mx, cmax(o));
+  }
+  if (rn.c) record_amax(rn.c, mx);
+}
+
 template <int PREC>
 struct LdsRow;  // bytes per complex element in LDS per plane
 template <> struct LdsRow<P_FP32> { static constexpr int elem = 8, planes = 1; };
@@ -115,7 +163,7 @@ template <int PREC, int WTM, int WTN>
 __global__ void __launch_bounds__(kThreads)
 cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
            float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, const uint32_t* amaxA,
-           const uint32_t* amaxB, Renorm rn) {
+           const uint32_t* amaxB, Renorm rn, int64_t kc, float2* __restrict__ P) {
   constexpr int BM = 32 * WTM, BN = 16 * WTN;
   using LA = TileLds<PREC, BM>;
   using LB = TileLds<PREC, BN>;
@@ -137,9 +185,14 @@ cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
   const int64_t tn = (bid % per_group) / gsize;
 
   const int64_t batch = blockIdx.z;
-  A += batch * sa + tm * BM * K;
-  B += batch * sb + tn * BN * K;
-  C += batch * sc;
+  const bool partial = gridDim.y > 1;
+  A += batch * sa + tm * BM * K + blockIdx.y * kc;
+  B += batch * sb + tn * BN * K + blockIdx.y * kc;
+  if (partial) {
+    C = P + ((int64_t)blockIdx.y * gridDim.z + batch) * M * N;
+  } else {
+    C += batch * sc;
+  }
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * (16 * WTM);   // wave's first row in the block tile
@@ -147,7 +200,7 @@ cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
   const int l16 = lane & 15, lg = lane >> 4;
 
   float scale_a, scale_b, unscale;
-  renorm_begin<PREC>(rn, amaxA, amaxB, scale_a, scale_b, unscale);
+  scales_for<PREC>(rn, amaxA, amaxB, partial, scale_a, scale_b, unscale);
 
   f4 acc[WTM][WTN];
 #pragma unroll
@@ -158,7 +211,7 @@ cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
   float4 ra[BM * 16 / kThreads], rb[BN * 16 / kThreads];
   load_tile<BM>(ra, A, K, 0);
   load_tile<BN>(rb, B, K, 0);
-  const int64_t nk = K / kBK;
+  const int64_t nk = kc / kBK;
   for (int64_t kt = 0; kt < nk; ++kt) {
     stage_tile<PREC, BM>(ldsA, ra, scale_a);
     stage_tile<PREC, BN>(ldsB, rb, scale_b);
@@ -252,7 +305,7 @@ cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
       C[(row + 1) * N + col] = o1;
       mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
     }
-  if (rn.c) record_amax(rn.c, mx);
+  if (rn.c && !partial) record_amax(rn.c, mx);
 }
 
 // Large shapes, BF16-family products: 512 threads = 8 waves as 4 (M) x 2 (N); a wave owns
@@ -331,7 +384,7 @@ template <int PREC>
 __global__ void __launch_bounds__(kV2Threads)
 cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
          float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, const uint32_t* amaxA, const uint32_t* amaxB,
-         Renorm rn) {
+         Renorm rn, int64_t kc, float2* __restrict__ P) {
   __shared__ __attribute__((aligned(16))) char lds[2 * V2<PREC>::stage];
   constexpr int planes = V2<PREC>::planes;
 
@@ -348,9 +401,14 @@ cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const fl
   const int64_t tn = (bid % per_group) / gsize;
 
   const int64_t batch = blockIdx.z;
-  A += batch * sa + tm * kV2BM * K;
-  B += batch * sb + tn * kV2BN * K;
-  C += batch * sc;
+  const bool partial = gridDim.y > 1;
+  A += batch * sa + tm * kV2BM * K + blockIdx.y * kc;
+  B += batch * sb + tn * kV2BN * K + blockIdx.y * kc;
+  if (partial) {
+    C = P + ((int64_t)blockIdx.y * gridDim.z + batch) * M * N;
+  } else {
+    C += batch * sc;
+  }
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * 64;  // first row of the wave
@@ -359,7 +417,7 @@ cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const fl
   const BExpand bx(q);
 
   float scale_a, scale_b, unscale;
-  renorm_begin<PREC>(rn, amaxA, amaxB, scale_a, scale_b, unscale);
+  scales_for<PREC>(rn, amaxA, amaxB, partial, scale_a, scale_b, unscale);
 
   f4 acc[4][8];
 #pragma unroll
@@ -368,7 +426,7 @@ cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const fl
     for (int j = 0; j < 8; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
 
   float4 ra[4], rb[2];
-  const int64_t nk = K / kV2BK;
+  const int64_t nk = kc / kV2BK;
   v2_load(ra, rb, A, B, K, 0);
   v2_store<PREC>(lds, ra, rb, scale_a, scale_b);
   if (nk > 1) v2_load(ra, rb, A, B, K, kV2BK);
@@ -435,7 +493,7 @@ cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const fl
       C[(row + 1) * N + col] = o1;
       mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
     }
-  if (rn.c) record_amax(rn.c, mx);
+  if (rn.c && !partial) record_amax(rn.c, mx);
 }
 
 // Small or thin shapes: one thread per output element, FP32 complex FMA over K.
@@ -559,11 +617,12 @@ cgemm_splitk(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, cons
 template <int PREC, int WTM, int WTN>
 static hipError_t launch_tiled(hipStream_t st, int64_t M, int64_t N, int64_t K, const float2* A,
                                const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb,
-                               int64_t sc, const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn) {
+                               int64_t sc, const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn,
+                               int split, float2* P) {
   constexpr int BM = 32 * WTM, BN = 16 * WTN;
   const int64_t tiles = (M / BM) * (N / BN);
-  hipLaunchKernelGGL((cgemm_mfma<PREC, WTM, WTN>), dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kThreads), 0, st,
-                     M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB, rn);
+  hipLaunchKernelGGL((cgemm_mfma<PREC, WTM, WTN>), dim3((unsigned)tiles, (unsigned)split, (unsigned)batch),
+                     dim3(kThreads), 0, st, M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB, rn, K / split, P);
   return hipGetLastError();
 }
 
@@ -608,26 +667,61 @@ int cgemm_default_variant(int precision, int64_t M, int64_t N, int64_t K) {
 template <int PREC>
 static hipError_t launch_mfma(hipStream_t st, int variant, int64_t M, int64_t N, int64_t K, const float2* A,
                               const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
-                              const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn) {
+                              const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn, int split,
+                              float2* P) {
   switch (variant) {
     case GEMM_LARGE:
       if constexpr (PREC != P_FP32) {
         const int64_t tiles = (M / kV2BM) * (N / kV2BN);
-        hipLaunchKernelGGL((cgemm_v2<PREC>), dim3((unsigned)tiles, 1, (unsigned)batch), dim3(kV2Threads), 0, st,
-                           M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB, rn);
+        hipLaunchKernelGGL((cgemm_v2<PREC>), dim3((unsigned)tiles, (unsigned)split, (unsigned)batch),
+                           dim3(kV2Threads), 0, st, M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB, rn, K / split, P);
         return hipGetLastError();
       }
       return hipErrorInvalidValue;
-    case GEMM_TILED_4X4: return launch_tiled<PREC, 4, 4>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
-    case GEMM_TILED_2X2: return launch_tiled<PREC, 2, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
-    case GEMM_TILED_1X2: return launch_tiled<PREC, 1, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+    case GEMM_TILED_4X4:
+      return launch_tiled<PREC, 4, 4>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn, split, P);
+    case GEMM_TILED_2X2:
+      return launch_tiled<PREC, 2, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn, split, P);
+    case GEMM_TILED_1X2:
+      return launch_tiled<PREC, 1, 2>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn, split, P);
   }
   return hipErrorInvalidValue;
 }
 
+// Workgroups of one launch of an MFMA variant (per batch element), and its K-tile length.
+static void variant_grid(int variant, int64_t M, int64_t N, int64_t* tiles, int64_t* bk) {
+  switch (variant) {
+    case GEMM_LARGE: *tiles = (M / kV2BM) * (N / kV2BN); *bk = kV2BK; return;
+    case GEMM_TILED_4X4: *tiles = (M / 128) * (N / 64); *bk = kBK; return;
+    case GEMM_TILED_2X2: *tiles = (M / 64) * (N / 32); *bk = kBK; return;
+    case GEMM_TILED_1X2: *tiles = (M / 32) * (N / 32); *bk = kBK; return;
+  }
+  *tiles = 0;
+  *bk = 0;
+}
+
+// K-chunks for an MFMA launch whose tile grid (per batch element) has fewer than 256 workgroups:
+// split K (powers of two, chunks of at least 4 K-tiles) towards about 1024 workgroups.  The count
+// depends on the shape only, so one contraction sums in the same order whatever the batch.
+static int split_count(int variant, int64_t M, int64_t N, int64_t K) {
+  int64_t tiles, bk;
+  variant_grid(variant, M, N, &tiles, &bk);
+  if (tiles <= 0 || tiles >= 256) return 1;
+  int split = 1;
+  while (split < 1024 && tiles * split * 2 <= 1024 && K / (split * 2) >= 4 * bk) split *= 2;
+  return split;
+}
+
+size_t cgemm_split_scratch(int precision, int64_t M, int64_t N, int64_t K, int64_t batch, int variant) {
+  if (variant == GEMM_AUTO) variant = cgemm_default_variant(precision, M, N, K);
+  const int split = split_count(variant, M, N, K);
+  return split > 1 ? (size_t)split * (size_t)(batch * M * N) * sizeof(float2) : 0;
+}
+
 hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
                            const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
-                           const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn, int variant) {
+                           const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn, int variant,
+                           float2* scratch, size_t scratch_bytes) {
   if (rn.c && (!rn.a || !rn.b)) return hipErrorInvalidValue;
   if (M < 1 || N < 1 || K < 1 || batch < 1) return hipErrorInvalidValue;
   if (precision != P_FP32 && precision != P_BF16X3 && precision != P_FP16) return hipErrorInvalidValue;
@@ -653,11 +747,25 @@ hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, 
       return hipGetLastError();
     }
   }
+  // split only when the caller's scratch holds every partial (otherwise one pass over K)
+  int split = scratch ? split_count(v, M, N, K) : 1;
+  if (split > 1 && (size_t)split * (size_t)(batch * M * N) * sizeof(float2) > scratch_bytes) split = 1;
+  hipError_t e;
   switch (precision) {
-    case P_FP32: return launch_mfma<P_FP32>(st, v, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
-    case P_BF16X3: return launch_mfma<P_BF16X3>(st, v, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
-    default: return launch_mfma<P_FP16>(st, v, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);
+    case P_FP32:
+      e = launch_mfma<P_FP32>(st, v, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn, split, scratch);
+      break;
+    case P_BF16X3:
+      e = launch_mfma<P_BF16X3>(st, v, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn, split, scratch);
+      break;
+    default:
+      e = launch_mfma<P_FP16>(st, v, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn, split, scratch);
   }
+  if (e != hipSuccess || split == 1) return e;
+  const int64_t total = batch * M * N;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(cgemm_split_reduce, dim3(blocks), dim3(256), 0, st, scratch, split, batch, M * N, sc, C, rn);
+  return hipGetLastError();
 }
 
 hipError_t launch_cgemm(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,

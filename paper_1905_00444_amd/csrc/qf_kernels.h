@@ -134,7 +134,10 @@ int cgemm_default_variant(int precision, int64_t M, int64_t N, int64_t K);
 hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
                            const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
                            const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn = Renorm{},
-                           int variant = GEMM_AUTO);
+                           int variant = GEMM_AUTO, float2* scratch = nullptr, size_t scratch_bytes = 0);
+// Bytes of scratch that lets an MFMA launch of this shape split K over more workgroups (0: the
+// launch fills the GPU without splitting, or its variant cannot split).
+size_t cgemm_split_scratch(int precision, int64_t M, int64_t N, int64_t K, int64_t batch, int variant = GEMM_AUTO);
 
 // p[i] = pseudo-random complex values, re and im uniform in [-1, 1) (hash of seed and i).
 hipError_t launch_fill_random(hipStream_t st, float2* p, int64_t n, uint32_t seed);

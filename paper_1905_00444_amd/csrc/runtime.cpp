@@ -151,6 +151,8 @@ struct qf_plan {
   size_t off_envwl = 0, off_bq = 0, off_bp = 0, off_bea = 0, off_beb = 0;
   std::vector<float2> gates_host;
   int64_t built_version = -1;
+  // partial tiles of GEMMs that split K (launches too small to fill the GPU)
+  size_t off_gscratch = 0, gscratch_bytes = 0;
   // power-of-two renormalisation: one NodeScale per node (leaves, then step results)
   bool renorm = false;
   size_t off_scales = 0;
@@ -568,6 +570,21 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     p->max_step_flops = std::max(p->max_step_flops, st.flops);
   }
 
+  // ---- split-K scratch: the largest need among the plan's GEMMs (forward, and the two
+  // environment GEMMs of each step in backward plans)
+  {
+    size_t need = 0;
+    for (const Step& st : p->steps) {
+      const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+      if (!st.presplit) need = std::max(need, cgemm_split_scratch(p->precision, M, N, K, p->G));
+      if (p->backward) {
+        need = std::max(need, cgemm_split_scratch(p->precision, M, K, N, 1));
+        need = std::max(need, cgemm_split_scratch(p->precision, N, K, M, 1));
+      }
+    }
+    p->gscratch_bytes = need;
+  }
+
   // ---- arena
   size_t cur = kCtxScratch;
   p->off_gates = cur;
@@ -599,6 +616,7 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     if (st.B.permute) trans.push_back({align_up(G * (sizeof(float2) << st.B.nbits)), i, i, &st.B.buf});
   }
   if (p->renorm) pers.push_back({align_up((n + S) * sizeof(NodeScale)), 0, S, &p->off_scales});
+  if (p->gscratch_bytes) pers.push_back({align_up(p->gscratch_bytes), 0, S, &p->off_gscratch});
   if (p->G > 1) {
     pers.push_back({align_up(n * sizeof(LeafDesc)), 0, S, &p->off_leafdesc});
     pers.push_back({align_up((size_t)p->G * n * sizeof(int64_t)), 0, S, &p->off_btable});
@@ -863,8 +881,9 @@ static qf_status plan_gemm(qf_plan* p, int64_t M, int64_t N, int64_t K, const fl
     auto it = c->tune.find({(int64_t)p->precision, M, N, K, batch});
     if (it != c->tune.end()) variant = it->second;
   }
+  float2* scratch = p->gscratch_bytes ? wsp(c, p->off_gscratch) : nullptr;
   QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, batch, M * K, N * K, M * N, amA, amB, rn,
-                            variant));
+                            variant, scratch, p->gscratch_bytes));
   return QF_OK;
 }
 
@@ -1256,8 +1275,16 @@ qf_status qf_cgemm(qf_ctx* c, int precision, int64_t M, int64_t N, int64_t K, co
     amA = slots;
     amB = slots + 1;
   }
+  // the context workspace beyond its slots holds split-K partials when it is large enough
+  float2* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  if (c->ws && c->ws_bytes > kCtxScratch) {
+    scratch = reinterpret_cast<float2*>(c->ws + kCtxScratch);
+    scratch_bytes = c->ws_bytes - kCtxScratch;
+  }
   QF_HIP(c, launch_cgemm_ex(c->stream, precision, M, N, K, reinterpret_cast<const float2*>(A),
-                            reinterpret_cast<const float2*>(B), reinterpret_cast<float2*>(C), batch, sa, sb, sc, amA, amB));
+                            reinterpret_cast<const float2*>(B), reinterpret_cast<float2*>(C), batch, sa, sb, sc, amA, amB,
+                            Renorm{}, GEMM_AUTO, scratch, scratch_bytes));
   return QF_OK;
 }
 
@@ -1446,13 +1473,15 @@ static std::string read_tune_file(const char* path, std::map<std::array<int64_t,
 
 // Average milliseconds of one GEMM launch of the given variant (a first launch warms up and is
 // used to size the repetitions: about 10 ms of work, 2 to 20 launches).  *ms < 0: not timed.
-static qf_status time_variant(qf_ctx* c, int prec, int variant, int64_t M, int64_t N, int64_t K, int64_t G,
-                              const float2* A, const float2* B, float2* C, float give_up_ms, float* ms) {
+static qf_status time_variant(qf_ctx* c, const qf_plan* p, int variant, int64_t M, int64_t N, int64_t K,
+                              int64_t G, const float2* A, const float2* B, float2* C, float give_up_ms, float* ms) {
+  const int prec = p->precision;
+  float2* scratch = p->gscratch_bytes ? reinterpret_cast<float2*>(c->ws + p->off_gscratch) : nullptr;
   hipEvent_t e0 = take_event(c), e1 = take_event(c);
   if (!e0 || !e1) return fail(c, QF_ERR_HIP, "hipEventCreate failed");
   auto launch = [&]() {
     return launch_cgemm_ex(c->stream, prec, M, N, K, A, B, C, G, M * K, N * K, M * N, nullptr, nullptr, Renorm{},
-                           variant);
+                           variant, scratch, p->gscratch_bytes);
   };
   *ms = -1.f;
   QF_HIP(c, hipEventRecord(e0, c->stream));
@@ -1538,7 +1567,7 @@ extern "C" qf_status qf_autotune(qf_ctx* c, const qf_plan* pc, const char* path)
     std::string times = "{";
     for (int v : tune_candidates(p->precision, M, N, K, G)) {
       float ms = 0.f;
-      qf_status e = time_variant(c, p->precision, v, M, N, K, G, A, B, C, best > 0 ? 3.f * best_ms : 0.f, &ms);
+      qf_status e = time_variant(c, p, v, M, N, K, G, A, B, C, best > 0 ? 3.f * best_ms : 0.f, &ms);
       if (e != QF_OK) return e;
       char buf[64];
       std::snprintf(buf, sizeof buf, "%s\"%s\": %.2f", times.size() > 1 ? ", " : "", kVariantName[v], 1e3 * ms);

@@ -92,6 +92,40 @@ def test_cgemm_matches_numpy(ctx, precision, M, N, K):
     assert err <= TOL[precision], err
 
 
+SPLIT_SHAPES = [(128, 64, 65536), (64, 32, 131072), (32, 32, 16384), (512, 512, 16384), (256, 128, 32768)]
+
+
+@pytest.fixture(scope="module")
+def split_ctx():
+    """A context whose workspace holds split-K partials (qf_cgemm then splits long-K launches
+    that have few output tiles)."""
+    from paper_1905_00444_amd import Context
+    c = Context(0)
+    c.ensure_workspace(256 << 20)
+    return c
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16"])
+@pytest.mark.parametrize("M,N,K", SPLIT_SHAPES)
+def test_cgemm_split_k_matches_numpy_and_is_deterministic(split_ctx, precision, M, N, K):
+    import torch
+    from paper_1905_00444_amd import cgemm
+    _say(f"cgemm split-K {precision} {M}x{N}x{K}")
+    rng = np.random.default_rng(M + N + K)
+    A = _rand_c64(rng, (M, K))
+    B = _rand_c64(rng, (N, K))
+    ref = A.astype(np.complex128) @ B.astype(np.complex128).T
+    bound = np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64).T
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C1 = cgemm(split_ctx, dA, dB, precision)
+    C2 = cgemm(split_ctx, dA, dB, precision)
+    torch.cuda.synchronize()
+    got = C1.cpu().numpy().astype(np.complex128)
+    err = np.max(np.abs(got - ref) / bound)
+    assert err <= TOL[precision], err
+    assert np.array_equal(C1.cpu().numpy(), C2.cpu().numpy())
+
+
 def test_cgemm_batched(ctx):
     import torch
     from paper_1905_00444_amd import _lib
