@@ -533,6 +533,9 @@ cgemm_simt(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
 // write consecutive 32-byte groups of C and the threads sharing a row read the same A row.
 constexpr int kSkinnyMaxB = 4096;  // complex elements of B held in LDS
 
+// B is held transposed in LDS (Bs[k][n]); thread (m, g) computes outputs n = g + t N/4 (t < 4), so
+// for each k the lanes of a wave read consecutive 8-byte words of one LDS row (no bank conflicts)
+// and write consecutive complex numbers of C (coalesced).  Each output sums k in ascending order.
 __global__ void __launch_bounds__(256)
 cgemm_skinny(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
              float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, Renorm rn) {
@@ -544,36 +547,38 @@ cgemm_skinny(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, cons
   A += batch * sa;
   B += batch * sb;
   C += batch * sc;
-  const int nk = (int)(N * K);
-  for (int i = threadIdx.x; i < nk; i += 256) Bs[i] = B[i];
+  const int n_ = (int)N, k_ = (int)K;
+  for (int i = threadIdx.x; i < n_ * k_; i += 256) {
+    const int n = i / k_, k = i - n * k_;
+    Bs[k * n_ + n] = B[i];
+  }
   __syncthreads();
-  const int64_t groups = N / 4;
-  const int64_t total = M * groups;
+  const int Q = n_ / 4;
+  const int64_t total = M * Q;
   for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < total; o += (int64_t)gridDim.x * 256) {
-    const int64_t m = o / groups;
-    const int g = (int)(o - m * groups);
+    const int64_t m = o / Q;
+    const int g = (int)(o - m * Q);
     const float2* a = A + m * K;
     float cr[4] = {0.f, 0.f, 0.f, 0.f}, ci[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < (int)K; ++k) {
+    for (int k = 0; k < k_; ++k) {
       const float2 x = a[k];
+      const float2* brow = Bs + k * n_ + g;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const float2 y = Bs[(4 * g + t) * K + k];
+        const float2 y = brow[t * Q];
         cr[t] = fmaf(x.x, y.x, cr[t]);
         cr[t] = fmaf(-x.y, y.y, cr[t]);
         ci[t] = fmaf(x.x, y.y, ci[t]);
         ci[t] = fmaf(x.y, y.x, ci[t]);
       }
     }
+    float2* out = C + m * N + g;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      cr[t] *= unscale;
-      ci[t] *= unscale;
-      mx = fmaxf(mx, fmaxf(fabsf(cr[t]), fabsf(ci[t])));
+      const float2 v = make_float2(cr[t] * unscale, ci[t] * unscale);
+      out[t * Q] = v;
+      mx = fmaxf(mx, cmax(v));
     }
-    float4* out = reinterpret_cast<float4*>(C + m * N + 4 * g);
-    out[0] = make_float4(cr[0], ci[0], cr[1], ci[1]);
-    out[1] = make_float4(cr[2], ci[2], cr[3], ci[3]);
   }
   if (rn.c) record_amax(rn.c, mx);
 }
