@@ -333,3 +333,13 @@ def tuned_variant(ctx: Context, precision: str, M: int, N: int, K: int, batch: i
     check(ctx.lib.qf_tuned_variant(ctx.h, PRECISIONS[precision], int(M), int(N), int(K), int(batch), C.byref(v)),
           ctx.h)
     return _lib.GEMM_VARIANTS[v.value]
+
+
+def amplitudes(circuit_text: str, plan: dict, bits, precision: str = "bf16x3", ctx: Optional[Context] = None,
+               s_begin: int = 0, s_end: Optional[int] = None):
+    """One-call form: amplitudes (n_batch, 2^n_open) complex128 on the device for the bitstrings
+    `bits` (n_batch x n, 0/1) of the circuit in text form, contracted with `plan` over slices
+    [s_begin, s_end) (all slices by default: the whole amplitudes)."""
+    ctx = ctx if ctx is not None else Context(0)
+    p = Plan(ctx, Circuit(ctx, circuit_text), plan, precision)
+    return p.amplitudes(bits, s_begin, s_end)

@@ -318,3 +318,15 @@ def test_7x7_d32_full_amplitudes_follow_porter_thomas(ctx):
     assert 1.0 <= m2 <= 3.2, m2
     assert ks <= 0.12, ks
     assert 0.5e-15 < np.mean(np.abs(got) ** 2) < 3e-15
+
+
+def test_one_call_amplitudes_function():
+    import torch
+    from paper_1905_00444_amd import amplitudes
+    _say("one-call amplitudes")
+    c = generate(4, 4, 16, 0)
+    bits = random_bitstrings(8, 16, 2)
+    got = amplitudes(c.to_text(), sweep_plan(c), bits, "fp32")
+    torch.cuda.synchronize()
+    assert got.dtype == torch.complex128 and got.shape == (8, 1)
+    assert rel_err(got.cpu().numpy()[:, 0], sv.amplitudes(c.to_text(), bits)) <= 1e-5
