@@ -35,10 +35,11 @@ def parse():
     ap.add_argument("--no-subcheck", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="launch one plain 1 GiB device copy first (HBM counter calibration)")
-    ap.add_argument("--workload", default="7x7-d40", choices=["7x7-d40", "8x9-d24", "6x6-d24-grad"],
+    ap.add_argument("--workload", default="7x7-d40", choices=["7x7-d40", "8x9-d24", "6x6-d24-grad", "vendor-gemm"],
                     help="7x7-d40: the benchmark line (default); 8x9-d24: 70 qubits, batched chains through a "
                          "captured graph, beside the searched plan; 6x6-d24-grad: forward and backward of 64 "
-                         "amplitudes")
+                         "amplitudes; vendor-gemm: the vendor real BF16 / FP32 GEMM on the same GPU (context for "
+                         "the roofline: what the matrix cores sustain under the power limit)")
     return ap.parse_args()
 
 
@@ -94,6 +95,29 @@ def bench_8x9(args):
                             "complex_tflops": 16 * q.info()["flops_per_slice"] / dt / 1e12,
                             "plan": repr(best), "rel_err_bf16x3_vs_fp32": float(norm(a - b) / norm(b))}
     print(json.dumps(rec), flush=True)
+    return 0
+
+
+def bench_vendor_gemm(args):
+    """Real square GEMMs through torch (hipBLASLt / rocBLAS) in BF16 and FP32 on this GPU."""
+    import torch
+    out = {"metric": "vendor real GEMM TFLOP/s (torch matmul)", "n_gpus": 1}
+    for dt, name in ((torch.bfloat16, "bf16"), (torch.float32, "fp32")):
+        for n in (8192, 16384):
+            a = torch.randn(n, n, device="cuda", dtype=dt)
+            b = torch.randn(n, n, device="cuda", dtype=dt)
+            for _ in range(3):
+                c = a @ b
+            torch.cuda.synchronize()
+            reps = 10 if n == 8192 else 4
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                c = a @ b
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / reps
+            out[f"{name}_{n}"] = {"ms": sec * 1e3, "tflops": 2.0 * n ** 3 / sec / 1e12}
+            del a, b, c
+    print(json.dumps(out), flush=True)
     return 0
 
 
@@ -232,6 +256,8 @@ def main():
         return bench_8x9(args)
     if args.workload == "6x6-d24-grad":
         return bench_6x6_grad(args)
+    if args.workload == "vendor-gemm":
+        return bench_vendor_gemm(args)
     import torch
     from paper_1905_00444_amd import Context, Circuit, Plan, profile_enable, profile_read
     from workloads.bitstrings import random_bitstrings
