@@ -79,24 +79,40 @@ __device__ __forceinline__ void scales_for(const Renorm& rn, const uint32_t* ama
   unscale = ldexpf(1.f, -(s_a + s_b));
 }
 
+// 32 lanes per output: lane t sums chunks [t split/32, (t+1) split/32) in order, then a fixed
+// butterfly over the 32 lanes; the summation order is the same on every run.
+constexpr int kReduceLanes = 32;
+
 __global__ void __launch_bounds__(256)
 cgemm_split_reduce(const float2* __restrict__ P, int split, int64_t batch, int64_t MN, int64_t sc,
                    float2* __restrict__ C, Renorm rn) {
   float sa_, sb_, unscale;
   renorm_begin<P_FP32>(rn, nullptr, nullptr, sa_, sb_, unscale);
   const int64_t total = batch * MN;
+  const int t = threadIdx.x % kReduceLanes;
+  const int per = split / kReduceLanes;  // split is a power of two >= 2
+  const int y0 = per > 0 ? t * per : (t < split ? t : split);
+  const int y1 = per > 0 ? y0 + per : (t < split ? t + 1 : split);
   float mx = 0.f;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kReduceLanes);
+  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / kReduceLanes) + threadIdx.x / kReduceLanes; i < total;
+       i += groups) {
     float re = 0.f, im = 0.f;
-    for (int y = 0; y < split; ++y) {
+    for (int y = y0; y < y1; ++y) {
       const float2 v = P[(int64_t)y * total + i];
       re += v.x;
       im += v.y;
     }
-    const float2 o = make_float2(re * unscale, im * unscale);
-    const int64_t b = i / MN;
-    C[b * sc + (i - b * MN)] = o;
-    mx = fmaxf(mx, cmax(o));
+    for (int off = kReduceLanes / 2; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, kReduceLanes);
+      im += __shfl_xor(im, off, kReduceLanes);
+    }
+    if (t == 0) {
+      const float2 o = make_float2(re * unscale, im * unscale);
+      const int64_t b = i / MN;
+      C[b * sc + (i - b * MN)] = o;
+      mx = fmaxf(mx, cmax(o));
+    }
   }
   if (rn.c) record_amax(rn.c, mx);
 }
@@ -768,7 +784,8 @@ hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, 
   }
   if (e != hipSuccess || split == 1) return e;
   const int64_t total = batch * M * N;
-  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  const int64_t per_block = 256 / kReduceLanes;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + per_block - 1) / per_block, 16384);
   hipLaunchKernelGGL(cgemm_split_reduce, dim3(blocks), dim3(256), 0, st, scratch, split, batch, M * N, sc, C, rn);
   return hipGetLastError();
 }

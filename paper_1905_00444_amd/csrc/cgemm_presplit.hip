@@ -212,14 +212,14 @@ template <bool DB>
 __global__ void __launch_bounds__(kV3Threads)
 cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
                   const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl, float2* __restrict__ C,
-                  int64_t sa, int64_t sb, int64_t sc, Renorm rn) {
+                  int64_t sa, int64_t sb, int64_t sc, Renorm rn, int group_rows) {
   __shared__ __attribute__((aligned(1024))) char lds[kV3Stages * kV3Stage];
 
   const int64_t tiles_m = M / kV3BM, tiles_n = N / kV3BN;
   const int64_t ntiles = tiles_m * tiles_n;
   int64_t bid = blockIdx.x;
   if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
-  const int64_t group = 8;
+  const int64_t group = group_rows;  // row tiles per raster group
   const int64_t per_group = group * tiles_n;
   const int64_t gidx = bid / per_group;
   const int64_t first_m = gidx * group;
@@ -347,6 +347,13 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
     return 3;
   }();
   const dim3 grid((unsigned)tiles, 1, (unsigned)batch);
+  // row tiles per raster group: the 32 workgroups that run together on one XCD then share 4 A
+  // panels and 8 B panels (QFMI_V3_GROUP overrides, comparison runs)
+  static const int group_rows = [] {
+    const char* e = getenv("QFMI_V3_GROUP");
+    const int g = e ? atoi(e) : 4;
+    return (g >= 1 && g <= 64) ? g : 4;
+  }();
   if (variant == 1)
     hipLaunchKernelGGL((cgemm_v3_presplit<4, 8>), grid, dim3(kV3Threads), 0, st, M, N, K, a, a + M * K, b, b + N * K,
                        C, 2 * sa, 2 * sb, sc, rn);
@@ -355,10 +362,10 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
                        C, 2 * sa, 2 * sb, sc, rn);
   else if (variant == 3)
     hipLaunchKernelGGL(cgemm_v4_presplit<false>, grid, dim3(kV3Threads), 0, st, M, N, K, a, a + M * K, b, b + N * K,
-                       C, 2 * sa, 2 * sb, sc, rn);
+                       C, 2 * sa, 2 * sb, sc, rn, group_rows);
   else
     hipLaunchKernelGGL(cgemm_v4_presplit<true>, grid, dim3(kV3Threads), 0, st, M, N, K, a, a + M * K, b, b + N * K,
-                       C, 2 * sa, 2 * sb, sc, rn);
+                       C, 2 * sa, 2 * sb, sc, rn, group_rows);
   return hipGetLastError();
 }
 
