@@ -512,6 +512,131 @@ cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const fl
   if (rn.c && !partial) record_amax(rn.c, mx);
 }
 
+// Large shapes in FP32: the same 256 x 128 block, 8 waves of 64 rows x 64 complex columns and
+// two register-staged LDS stages as above, with v_mfma_f32_16x16x4_f32 on the FP32 operands.
+// An MFMA step covers 4 real k; lane l supplies A[row l%16][real k = 4s + l/16] and the B entry of
+// real column (n, q = l & 1) at the same k: br or bi chosen by address (part ^ q), negated for
+// (q = 0, odd k).  LDS rows are 16 complex plus 8 bytes (34 dwords, 2 mod 32), so the 4-byte
+// operand reads of 16 rows x 2 neighbouring k hit 32 distinct banks.
+constexpr int kF32Row = 136;                      // bytes per LDS row
+constexpr int kF32PlaneA = kV2BM * kF32Row;       // 34 KiB
+constexpr int kF32PlaneB = kV2BN * kF32Row;       // 17 KiB
+constexpr int kF32Stage = kF32PlaneA + kF32PlaneB;
+
+__device__ __forceinline__ void f32_store(char* st, const float4 (&ra)[4], const float4 (&rb)[2]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = (tid >> 3) + 64 * i, c = tid & 7;  // c: complex pair 2c, 2c+1
+    float2* dst = reinterpret_cast<float2*>(st + row * kF32Row + c * 16);
+    dst[0] = make_float2(ra[i].x, ra[i].y);
+    dst[1] = make_float2(ra[i].z, ra[i].w);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int row = (tid >> 3) + 64 * i, c = tid & 7;
+    float2* dst = reinterpret_cast<float2*>(st + kF32PlaneA + row * kF32Row + c * 16);
+    dst[0] = make_float2(rb[i].x, rb[i].y);
+    dst[1] = make_float2(rb[i].z, rb[i].w);
+  }
+}
+
+__global__ void __launch_bounds__(kV2Threads)
+cgemm_v2f32(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
+            float2* __restrict__ C, int64_t sa, int64_t sb, int64_t sc, Renorm rn, int64_t kc,
+            float2* __restrict__ P) {
+  __shared__ __attribute__((aligned(16))) char lds[2 * kF32Stage];
+
+  const int64_t tiles_m = M / kV2BM, tiles_n = N / kV2BN;
+  const int64_t ntiles = tiles_m * tiles_n;
+  int64_t bid = blockIdx.x;
+  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
+  const int64_t group = 4;
+  const int64_t per_group = group * tiles_n;
+  const int64_t gidx = bid / per_group;
+  const int64_t first_m = gidx * group;
+  const int64_t gsize = (tiles_m - first_m) < group ? (tiles_m - first_m) : group;
+  const int64_t tm = first_m + (bid % per_group) % gsize;
+  const int64_t tn = (bid % per_group) / gsize;
+
+  const int64_t batch = blockIdx.z;
+  const bool partial = gridDim.y > 1;
+  A += batch * sa + tm * kV2BM * K + blockIdx.y * kc;
+  B += batch * sb + tn * kV2BN * K + blockIdx.y * kc;
+  if (partial) {
+    C = P + ((int64_t)blockIdx.y * gridDim.z + batch) * M * N;
+  } else {
+    C += batch * sc;
+  }
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 64;
+  const int wc = (wave & 1) * 64;
+  const int l16 = lane & 15, lg = lane >> 4, q = l16 & 1;
+  // A: dword 4s + lg of the row; B: dword 4s + 2 (lg >> 1) + ((lg & 1) ^ q), sign bit flipped
+  // for (q = 0, odd real k)
+  const int b_word = 2 * (lg >> 1) + ((lg & 1) ^ q);
+  const uint32_t b_flip = (q == 0 && (lg & 1)) ? 0x80000000u : 0u;
+
+  float scale_a, scale_b, unscale;
+  scales_for<P_FP32>(rn, nullptr, nullptr, partial, scale_a, scale_b, unscale);
+
+  f4 acc[4][8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+
+  float4 ra[4], rb[2];
+  const int64_t nk = kc / kV2BK;
+  v2_load(ra, rb, A, B, K, 0);
+  f32_store(lds, ra, rb);
+  if (nk > 1) v2_load(ra, rb, A, B, K, kV2BK);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const char* st = lds + (kt & 1) * kF32Stage;
+    const float* LA = reinterpret_cast<const float*>(st);
+    const float* LB = reinterpret_cast<const float*>(st + kF32PlaneA);
+#pragma unroll 2
+    for (int s4 = 0; s4 < kV2BK / 2; ++s4) {  // 8 MFMA steps of 4 real k
+      float a[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = LA[(wr + 16 * i + l16) * (kF32Row / 4) + 4 * s4 + lg];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float braw = LB[(wc + 8 * j + (l16 >> 1)) * (kF32Row / 4) + 4 * s4 + b_word];
+        const float b = __uint_as_float(__float_as_uint(braw) ^ b_flip);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b, acc[i][j], 0, 0, 0);
+      }
+    }
+    if (kt + 1 < nk) {
+      f32_store(lds + ((kt + 1) & 1) * kF32Stage, ra, rb);
+      if (kt + 2 < nk) v2_load(ra, rb, A, B, K, (kt + 2) * kV2BK);
+    }
+    __syncthreads();
+  }
+
+  float mx = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const f4 v = acc[i][j] * unscale;
+      const float s0 = q ? v[0] : v[2], s1 = q ? v[1] : v[3];
+      const float r0 = __shfl_xor(s0, 1), r1 = __shfl_xor(s1, 1);
+      const int64_t row = tm * kV2BM + wr + 16 * i + 4 * lg + (q ? 2 : 0);
+      const int64_t col = tn * kV2BN + wc + 8 * j + (l16 >> 1);
+      float2 o0, o1;
+      if (q) { o0 = make_float2(r0, v[2]); o1 = make_float2(r1, v[3]); }
+      else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
+      C[row * N + col] = o0;
+      C[(row + 1) * N + col] = o1;
+      mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
+    }
+  if (rn.c && !partial) record_amax(rn.c, mx);
+}
+
 // Small or thin shapes: one thread per output element, FP32 complex FMA over K.
 __global__ void __launch_bounds__(256)
 cgemm_simt(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const float2* __restrict__ B,
@@ -665,7 +790,7 @@ bool cgemm_variant_fits(int precision, int64_t M, int64_t N, int64_t K, int vari
     case GEMM_TILED_4X4: return p2 && M >= 128 && N >= 64 && K >= kBK;
     case GEMM_TILED_2X2: return p2 && M >= 64 && N >= 32 && K >= kBK;
     case GEMM_TILED_1X2: return p2 && M >= 32 && N >= 32 && K >= kBK;
-    case GEMM_LARGE: return p2 && precision != P_FP32 && M >= kV2BM && N >= kV2BN && K >= kV2BK;
+    case GEMM_LARGE: return p2 && M >= kV2BM && N >= kV2BN && K >= kV2BK;
     case GEMM_SKINNY: return N >= 4 && (N & 3) == 0 && N * K <= kSkinnyMaxB && K <= 64;
     case GEMM_SPLITK: return M * N <= 4096;
     case GEMM_SIMT: return M >= 1 && N >= 1 && K >= 1;
@@ -691,14 +816,16 @@ static hipError_t launch_mfma(hipStream_t st, int variant, int64_t M, int64_t N,
                               const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn, int split,
                               float2* P) {
   switch (variant) {
-    case GEMM_LARGE:
-      if constexpr (PREC != P_FP32) {
-        const int64_t tiles = (M / kV2BM) * (N / kV2BN);
+    case GEMM_LARGE: {
+      const int64_t tiles = (M / kV2BM) * (N / kV2BN);
+      if constexpr (PREC == P_FP32)
+        hipLaunchKernelGGL(cgemm_v2f32, dim3((unsigned)tiles, (unsigned)split, (unsigned)batch), dim3(kV2Threads), 0,
+                           st, M, N, K, A, B, C, sa, sb, sc, rn, K / split, P);
+      else
         hipLaunchKernelGGL((cgemm_v2<PREC>), dim3((unsigned)tiles, (unsigned)split, (unsigned)batch),
                            dim3(kV2Threads), 0, st, M, N, K, A, B, C, sa, sb, sc, amaxA, amaxB, rn, K / split, P);
-        return hipGetLastError();
-      }
-      return hipErrorInvalidValue;
+      return hipGetLastError();
+    }
     case GEMM_TILED_4X4:
       return launch_tiled<PREC, 4, 4>(st, M, N, K, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn, split, P);
     case GEMM_TILED_2X2:
