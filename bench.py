@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--cpu-reps", type=int, default=10, help="prefixes in the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-subcheck", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip timing the GEMM kernel variants of the plans' shapes before the warmup")
     ap.add_argument("--calib-copy", action="store_true",
                     help="launch one plain 1 GiB device copy first (HBM counter calibration)")
     ap.add_argument("--workload", default="7x7-d40", choices=["7x7-d40", "8x9-d24", "6x6-d24-grad", "vendor-gemm"],
@@ -259,7 +261,7 @@ def main():
     if args.workload == "vendor-gemm":
         return bench_vendor_gemm(args)
     import torch
-    from paper_1905_00444_amd import Context, Circuit, Plan, profile_enable, profile_read
+    from paper_1905_00444_amd import Context, Circuit, Plan, profile_enable, profile_read, autotune
     from workloads.bitstrings import random_bitstrings
     from workloads.circuits import generate
     from workloads.plans import plan_7x7
@@ -290,6 +292,16 @@ def main():
                 r.append([x, x + 1])
         runs.append(r)
     step_flops = [sum(plans["bf16x3"].flops(a, e) for a, e in r) for r in runs]
+
+    if not args.no_autotune:
+        # per-shape kernel choice for the plans' GEMMs (held in the context; untimed set-up)
+        for prec in ("bf16x3", "fp32"):
+            if prec == "fp32" and args.fp32_steps <= 0:
+                continue
+            t0 = time.perf_counter()
+            autotune(plans[prec])
+            torch.cuda.synchronize()
+            print(f"bench: autotune {prec} {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
     if args.calib_copy:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
