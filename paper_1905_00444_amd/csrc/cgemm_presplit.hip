@@ -208,7 +208,7 @@ __device__ __forceinline__ void v4_rows(const char* st, int wr, int l16, int a_c
 // the barrier and then streams A row group by row group, the compiler overlapping the A reads of
 // one group with the MFMAs of the previous.  DB = true keeps two B fragment sets in registers
 // (256 VGPRs, which leaves the compiler no room to overlap the A reads; slower).
-template <bool DB>
+template <bool DB, bool PRIO = false>
 __global__ void __launch_bounds__(kV3Threads)
 cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
                   const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl, float2* __restrict__ C,
@@ -262,7 +262,9 @@ cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
       const char* st = lds + (kt % kV3Stages) * kV3Stage;
       u4 bh[WJ], bl[WJ];
       v4_load_b(st, wc, l16, lg, bx, bh, bl);
+      if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);  // favour waves that are issuing MFMAs
       v4_rows<0, WI>(st, wr, l16, a_chunk, bh, bl, acc);
+      if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
     }
   }
   if constexpr (DB) {
@@ -344,6 +346,7 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
     if (e && std::string(e) == "64x64") return 1;
     if (e && std::string(e) == "128x32") return 2;
     if (e && std::string(e) == "db") return 0;
+    if (e && std::string(e) == "prio") return 4;
     return 3;
   }();
   const dim3 grid((unsigned)tiles, 1, (unsigned)batch);
@@ -363,6 +366,9 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
   else if (variant == 3)
     hipLaunchKernelGGL(cgemm_v4_presplit<false>, grid, dim3(kV3Threads), 0, st, M, N, K, a, a + M * K, b, b + N * K,
                        C, 2 * sa, 2 * sb, sc, rn, group_rows);
+  else if (variant == 4)
+    hipLaunchKernelGGL((cgemm_v4_presplit<false, true>), grid, dim3(kV3Threads), 0, st, M, N, K, a, a + M * K, b,
+                       b + N * K, C, 2 * sa, 2 * sb, sc, rn, group_rows);
   else
     hipLaunchKernelGGL(cgemm_v4_presplit<true>, grid, dim3(kV3Threads), 0, st, M, N, K, a, a + M * K, b, b + N * K,
                        C, 2 * sa, 2 * sb, sc, rn, group_rows);
