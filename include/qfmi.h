@@ -200,6 +200,15 @@ qf_status qf_cgemm(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, 
                    const void* B, void* C, int64_t batch, int64_t stride_a, int64_t stride_b,
                    int64_t stride_c);
 
+/* Same as qf_cgemm with an explicit kernel variant (comparison runs and tests):
+ *   0 auto, 1 tiled 128 x 64, 2 tiled 64 x 32, 3 tiled 32 x 32, 4 large 256 x 128, 5 skinny
+ *   (SIMT FP32, B in LDS), 6 split-K reduction per output, 7 one thread per output, 8 tall
+ *   (M large, powers of two with 8 <= N <= 64 and 16 <= K <= 64: B in LDS, A streamed).
+ * QF_ERR_UNSUPPORTED if the variant does not fit the shape, QF_ERR_ARG if it is unknown. */
+qf_status qf_cgemm_variant(qf_ctx* ctx, int precision, int variant, int64_t M, int64_t N, int64_t K,
+                           const void* A, const void* B, void* C, int64_t batch, int64_t sa, int64_t sb,
+                           int64_t sc);
+
 /* Split-BF16 operand (the conversion the split-BF16 GEMM consumes, Sec. III-E's "T" step
  * writes it directly when it precedes such a GEMM): for j < 2^nbits complex64 src[j] = x,
  * writes hi = bf16(x) (round to nearest even, re and im) into 32-bit word j of dst and

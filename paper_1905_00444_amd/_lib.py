@@ -17,7 +17,7 @@ QF_PLAN_NO_HOIST = 1
 QF_PLAN_BACKWARD = 2
 QF_PLAN_GRAPH = 4
 QF_PLAN_NO_RENORM = 8
-GEMM_VARIANTS = ("auto", "tiled4x4", "tiled2x2", "tiled1x2", "large", "skinny", "splitk", "simt")
+GEMM_VARIANTS = ("auto", "tiled4x4", "tiled2x2", "tiled1x2", "large", "skinny", "splitk", "simt", "tall")
 
 STATUS_NAMES = {0: "QF_OK", -1: "QF_ERR_ARG", -2: "QF_ERR_PLAN", -3: "QF_ERR_WORKSPACE", -4: "QF_ERR_HIP",
                 -5: "QF_ERR_UNSUPPORTED", -6: "QF_ERR_INJECTED"}
@@ -66,6 +66,8 @@ EXPORTS = {
                              C.c_float]),
     "qf_cgemm": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int64]),
+    "qf_cgemm_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int64]),
     "qf_split_bf16": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "qf_cgemm_presplit": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "qf_time_cgemm_presplit": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,

@@ -240,8 +240,9 @@ def permute(ctx: Context, src, dst, perm: Sequence[int], base: int = 0, scale: f
                              p.ctypes.data_as(C.POINTER(C.c_int32)), int(base), float(scale)), ctx.h)
 
 
-def cgemm(ctx: Context, A, B, precision: str = "fp32", out=None):
-    """C[m, n] = sum_k A[m, k] B[n, k] (complex64, no conjugation)."""
+def cgemm(ctx: Context, A, B, precision: str = "fp32", out=None, variant: str = "auto"):
+    """C[m, n] = sum_k A[m, k] B[n, k] (complex64, no conjugation); `variant` names a kernel
+    variant (one of _lib.GEMM_VARIANTS) instead of the shape's default."""
     torch = _torch()
     M, K = A.shape
     N, K2 = B.shape
@@ -252,8 +253,9 @@ def cgemm(ctx: Context, A, B, precision: str = "fp32", out=None):
         out = torch.empty((M, N), dtype=torch.complex64, device=A.device)
     if precision == "fp16":
         ctx.ensure_workspace(4096)
-    check(ctx.lib.qf_cgemm(ctx.h, PRECISIONS[precision], M, N, K, C.c_void_p(A.data_ptr()),
-                           C.c_void_p(B.data_ptr()), C.c_void_p(out.data_ptr()), 1, 0, 0, 0), ctx.h)
+    check(ctx.lib.qf_cgemm_variant(ctx.h, PRECISIONS[precision], _lib.GEMM_VARIANTS.index(variant), M, N, K,
+                                   C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()), C.c_void_p(out.data_ptr()),
+                                   1, 0, 0, 0), ctx.h)
     return out
 
 

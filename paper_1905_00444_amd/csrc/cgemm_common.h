@@ -73,10 +73,17 @@ __device__ __forceinline__ void renorm_begin(const Renorm& rn, const uint32_t* a
 
 __device__ __forceinline__ float cmax(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
 
-// Wave-wide max of m, one atomic per wave into c->amax (every lane of the wave must call).
+// Wave-wide max of m, raised into c->amax (every lane of the wave must call).  All waves of a
+// launch target one address, and atomics on one address are serialised (about 10 ns each: two
+// million waves cost 20 ms), so a wave first reads the current value from L2 and issues the
+// atomic only if it holds a larger one.  amax only grows during the launch, so the value read is
+// a lower bound of the final one and skipping is exact.
 __device__ __forceinline__ void record_amax(NodeScale* c, float m) {
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-  if ((threadIdx.x & 63) == 0) atomicMax(&c->amax, __float_as_uint(m));
+  if ((threadIdx.x & 63) == 0) {
+    const uint32_t v = __float_as_uint(m);
+    if (v > __hip_atomic_load(&c->amax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&c->amax, v);
+  }
 }
 
 

@@ -31,7 +31,7 @@ constexpr int kV3LoadsPerWave = (kV3Stage / 1024) / (kV3Threads / 64);  // 6
 
 __device__ __forceinline__ void v3_issue(char* stage, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
                                          const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl,
-                                         int64_t K, int64_t k0, int wave, int lane) {
+                                         int64_t lda, int64_t ldb, int64_t k0, int wave, int lane) {
   const int r = lane >> 2, pos = lane & 3;
   const int c = pos ^ ((r >> 1) & 3);
 #pragma unroll
@@ -41,11 +41,11 @@ __device__ __forceinline__ void v3_issue(char* stage, const uint32_t* __restrict
     int off;
     if (q < 32) {
       const int plane = q >> 4, r0 = (q & 15) * 16;
-      src = (plane ? Al : Ah) + (int64_t)(r0 + r) * K + k0 + 4 * c;
+      src = (plane ? Al : Ah) + (int64_t)(r0 + r) * lda + k0 + 4 * c;
       off = plane * kV3PlaneA + r0 * 64;
     } else {
       const int qq = q - 32, plane = qq >> 3, r0 = (qq & 7) * 16;
-      src = (plane ? Bl : Bh) + (int64_t)(r0 + r) * K + k0 + 4 * c;
+      src = (plane ? Bl : Bh) + (int64_t)(r0 + r) * ldb + k0 + 4 * c;
       off = 2 * kV3PlaneA + plane * kV3PlaneB + r0 * 64;
     }
     __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)(stage + off), 16, 0, 0);
@@ -59,7 +59,7 @@ template <int WI, int WJ>
 __global__ void __launch_bounds__(kV3Threads)
 cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
                   const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl, float2* __restrict__ C,
-                  int64_t sa, int64_t sb, int64_t sc, Renorm rn) {
+                  int64_t lda, int64_t ldb, int64_t sa, int64_t sb, int64_t sc, Renorm rn) {
   __shared__ __attribute__((aligned(1024))) char lds[kV3Stages * kV3Stage];
 
   const int64_t tiles_m = M / kV3BM, tiles_n = N / kV3BN;
@@ -75,10 +75,10 @@ cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
   const int64_t tn = (bid % per_group) / gsize;
 
   const int64_t batch = blockIdx.z;
-  Ah += batch * sa + tm * kV3BM * K;
-  Al += batch * sa + tm * kV3BM * K;
-  Bh += batch * sb + tn * kV3BN * K;
-  Bl += batch * sb + tn * kV3BN * K;
+  Ah += batch * sa + tm * kV3BM * lda;
+  Al += batch * sa + tm * kV3BM * lda;
+  Bh += batch * sb + tn * kV3BN * ldb;
+  Bl += batch * sb + tn * kV3BN * ldb;
   C += batch * sc;
 
   static_assert(WI * WJ == 32 && 16 * WI <= kV3BM && 8 * WJ <= kV3BN, "8 waves cover the block tile");
@@ -98,13 +98,13 @@ cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
     for (int j = 0; j < WJ; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
 
   const int64_t nk = K / kV3BK;
-  v3_issue(lds, Ah, Al, Bh, Bl, K, 0, wave, lane);
-  if (nk > 1) v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, K, kV3BK, wave, lane);
+  v3_issue(lds, Ah, Al, Bh, Bl, lda, ldb, 0, wave, lane);
+  if (nk > 1) v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, lda, ldb, kV3BK, wave, lane);
   for (int64_t kt = 0; kt < nk; ++kt) {
     if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
     else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __builtin_amdgcn_s_barrier();
-    if (kt + 2 < nk) v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, K, (kt + 2) * kV3BK, wave, lane);
+    if (kt + 2 < nk) v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, lda, ldb, (kt + 2) * kV3BK, wave, lane);
     const char* st = lds + (kt % kV3Stages) * kV3Stage;
     u4 ah[WI], al[WI];
 #pragma unroll
@@ -208,11 +208,11 @@ __device__ __forceinline__ void v4_rows(const char* st, int wr, int l16, int a_c
 // the barrier and then streams A row group by row group, the compiler overlapping the A reads of
 // one group with the MFMAs of the previous.  DB = true keeps two B fragment sets in registers
 // (256 VGPRs, which leaves the compiler no room to overlap the A reads; slower).
-template <bool DB, bool PRIO = false>
+template <bool DB>
 __global__ void __launch_bounds__(kV3Threads)
 cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
                   const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl, float2* __restrict__ C,
-                  int64_t sa, int64_t sb, int64_t sc, Renorm rn, int group_rows) {
+                  int64_t lda, int64_t ldb, int64_t sa, int64_t sb, int64_t sc, Renorm rn, int group_rows) {
   __shared__ __attribute__((aligned(1024))) char lds[kV3Stages * kV3Stage];
 
   const int64_t tiles_m = M / kV3BM, tiles_n = N / kV3BN;
@@ -228,10 +228,10 @@ cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
   const int64_t tn = (bid % per_group) / gsize;
 
   const int64_t batch = blockIdx.z;
-  Ah += batch * sa + tm * kV3BM * K;
-  Al += batch * sa + tm * kV3BM * K;
-  Bh += batch * sb + tn * kV3BN * K;
-  Bl += batch * sb + tn * kV3BN * K;
+  Ah += batch * sa + tm * kV3BM * lda;
+  Al += batch * sa + tm * kV3BM * lda;
+  Bh += batch * sb + tn * kV3BN * ldb;
+  Bl += batch * sb + tn * kV3BN * ldb;
   C += batch * sc;
 
   constexpr int WI = kV4WI, WJ = kV4WJ;
@@ -251,26 +251,24 @@ cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
 
   const int64_t nk = K / kV3BK;
   if constexpr (!DB) {
-    v3_issue(lds, Ah, Al, Bh, Bl, K, 0, wave, lane);
-    if (nk > 1) v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, K, kV3BK, wave, lane);
+    v3_issue(lds, Ah, Al, Bh, Bl, lda, ldb, 0, wave, lane);
+    if (nk > 1) v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, lda, ldb, kV3BK, wave, lane);
     for (int64_t kt = 0; kt < nk; ++kt) {
       if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
       else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __builtin_amdgcn_s_barrier();
       if (kt + 2 < nk)
-        v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, K, (kt + 2) * kV3BK, wave, lane);
+        v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, lda, ldb, (kt + 2) * kV3BK, wave, lane);
       const char* st = lds + (kt % kV3Stages) * kV3Stage;
       u4 bh[WJ], bl[WJ];
       v4_load_b(st, wc, l16, lg, bx, bh, bl);
-      if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);  // favour waves that are issuing MFMAs
       v4_rows<0, WI>(st, wr, l16, a_chunk, bh, bl, acc);
-      if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
     }
   }
   if constexpr (DB) {
-  v3_issue(lds, Ah, Al, Bh, Bl, K, 0, wave, lane);
+  v3_issue(lds, Ah, Al, Bh, Bl, lda, ldb, 0, wave, lane);
   if (nk > 1) {
-    v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, K, kV3BK, wave, lane);
+    v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, lda, ldb, kV3BK, wave, lane);
     asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
   } else {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -287,7 +285,7 @@ cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's loads of tile kt+1
       __builtin_amdgcn_s_barrier();                      // everyone's loads of kt+1; everyone past tile kt-1
       if (kt + 2 < nk)
-        v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, K, (kt + 2) * kV3BK, wave, lane);
+        v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, lda, ldb, (kt + 2) * kV3BK, wave, lane);
       v4_load_b(lds + ((kt + 1) % kV3Stages) * kV3Stage, wc, l16, lg, bx, nbh, nbl);
     }
     v4_rows<WI / 2, WI>(st, wr, l16, a_chunk, bh, bl, acc);
@@ -325,28 +323,34 @@ bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K) {
   return p2(M) && p2(N) && p2(K) && M >= kV3BM && N >= kV3BN && K >= kV3BK;
 }
 
-// A, B: split operands, each a hi plane followed by a lo plane (rows x K bfloat16 pairs each),
-// batch strides in complex elements of one plane-pair (= rows * K).
+// A, B: split operands, each a hi plane followed by a lo plane (rows x K bfloat16 pairs each,
+// consecutive rows lda (ldb) words apart, the lo plane rows * lda (rows * ldb) words after the hi
+// plane), batch strides in complex elements of one plane-pair (= rows * ld).
 hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
-                                 float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc, const Renorm& rn) {
+                                 float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc, const Renorm& rn,
+                                 int64_t lda, int64_t ldb) {
   if (!cgemm_presplit_fits(M, N, K)) return hipErrorInvalidValue;
+  if (lda == 0) lda = K;
+  if (ldb == 0) ldb = K;
+  if (lda < K || ldb < K || (lda & 3) || (ldb & 3)) return hipErrorInvalidValue;
   if (rn.c) {
     const hipError_t e = launch_renorm_reset(st, rn.c);
     if (e != hipSuccess) return e;
   }
   const uint32_t* a = reinterpret_cast<const uint32_t*>(A);
   const uint32_t* b = reinterpret_cast<const uint32_t*>(B);
+  const uint32_t* al = a + M * lda;
+  const uint32_t* bl = b + N * ldb;
   const int64_t tiles = (M / kV3BM) * (N / kV3BN);
-  // a batch element's region holds its hi plane then its lo plane: 2 * rows * K words
   // QFMI_V3_WAVES=64x64 / 128x32 / db select the other schedules (comparison runs); the default
   // streams A row groups against B fragments read at the start of each K-tile (fastest measured:
-  // 430 vs 423 (128x32), 408 (64x64) and 398 (db) TFLOP/s on 8192^3 and 2^15-cubed)
+  // 430 vs 423 (128x32), 408 (64x64) and 398 (db) TFLOP/s on 8192^3 and 2^15-cubed; raising the
+  // wave priority around the MFMAs measured 2% slower)
   static const int variant = [] {
     const char* e = getenv("QFMI_V3_WAVES");
     if (e && std::string(e) == "64x64") return 1;
     if (e && std::string(e) == "128x32") return 2;
     if (e && std::string(e) == "db") return 0;
-    if (e && std::string(e) == "prio") return 4;
     return 3;
   }();
   const dim3 grid((unsigned)tiles, 1, (unsigned)batch);
@@ -358,20 +362,17 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
     return (g >= 1 && g <= 64) ? g : 4;
   }();
   if (variant == 1)
-    hipLaunchKernelGGL((cgemm_v3_presplit<4, 8>), grid, dim3(kV3Threads), 0, st, M, N, K, a, a + M * K, b, b + N * K,
-                       C, 2 * sa, 2 * sb, sc, rn);
+    hipLaunchKernelGGL((cgemm_v3_presplit<4, 8>), grid, dim3(kV3Threads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb,
+                       2 * sa, 2 * sb, sc, rn);
   else if (variant == 2)
-    hipLaunchKernelGGL((cgemm_v3_presplit<8, 4>), grid, dim3(kV3Threads), 0, st, M, N, K, a, a + M * K, b, b + N * K,
-                       C, 2 * sa, 2 * sb, sc, rn);
+    hipLaunchKernelGGL((cgemm_v3_presplit<8, 4>), grid, dim3(kV3Threads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb,
+                       2 * sa, 2 * sb, sc, rn);
   else if (variant == 3)
-    hipLaunchKernelGGL(cgemm_v4_presplit<false>, grid, dim3(kV3Threads), 0, st, M, N, K, a, a + M * K, b, b + N * K,
-                       C, 2 * sa, 2 * sb, sc, rn, group_rows);
-  else if (variant == 4)
-    hipLaunchKernelGGL((cgemm_v4_presplit<false, true>), grid, dim3(kV3Threads), 0, st, M, N, K, a, a + M * K, b,
-                       b + N * K, C, 2 * sa, 2 * sb, sc, rn, group_rows);
+    hipLaunchKernelGGL(cgemm_v4_presplit<false>, grid, dim3(kV3Threads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb,
+                       2 * sa, 2 * sb, sc, rn, group_rows);
   else
-    hipLaunchKernelGGL(cgemm_v4_presplit<true>, grid, dim3(kV3Threads), 0, st, M, N, K, a, a + M * K, b, b + N * K,
-                       C, 2 * sa, 2 * sb, sc, rn, group_rows);
+    hipLaunchKernelGGL(cgemm_v4_presplit<true>, grid, dim3(kV3Threads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb,
+                       2 * sa, 2 * sb, sc, rn, group_rows);
   return hipGetLastError();
 }
 

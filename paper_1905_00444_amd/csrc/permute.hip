@@ -40,6 +40,9 @@ struct PermKernelArgs {
   const int64_t* base_table;
   int base_stride;
   int split;
+  int split_kbits;          // padded split rows: row = index >> split_kbits, ...
+  int64_t split_ld;         // ... at split_ld words apart (0: dense)
+  int64_t split_plane;      // words from the hi plane to the lo plane
 };
 
 __device__ __forceinline__ uint32_t bf16_pair(float re, float im) {
@@ -64,35 +67,54 @@ permute_kernel(const float2* __restrict__ src, float2* __restrict__ dst, PermKer
     sbase += bit << a.o_src[i];
     dbase += bit << a.o_dst[i];
   }
-  const int tvol = 1 << a.t;
-  for (int u = threadIdx.x; u < tvol; u += kPermThreads) {
-    int64_t off = 0;
+  // Tile index bits 0..7 come from the thread, bits 8..t-1 from the loop counter; offsets are ORs
+  // of disjoint bit contributions, so the thread's part is computed once.
+  const int tid = threadIdx.x, t = a.t;
+  const int lowb = t < 8 ? t : 8;
+  const int tvol = 1 << t;
+  const int iters = tvol >> lowb;
+  int64_t r_lo = 0, w_lo = 0;
+  int u_lo = 0;
 #pragma unroll
-    for (int i = 0; i < kPermMaxTile; ++i)
-      if (i < a.t) off |= (int64_t)((u >> i) & 1) << a.u_src[i];
-    tile[lds_index(u)] = src[sbase + off];
+  for (int i = 0; i < 8; ++i)
+    if (i < lowb) {
+      const int bit = (tid >> i) & 1;
+      r_lo |= (int64_t)bit << a.u_src[i];
+      w_lo |= (int64_t)bit << a.v_dst[i];
+      u_lo |= bit << a.v_to_u[i];
+    }
+  if (tid < tvol) {
+    for (int it = 0; it < iters; ++it) {
+      int64_t off = r_lo;
+#pragma unroll
+      for (int i = 8; i < kPermMaxTile; ++i)
+        if (i < t && ((it >> (i - 8)) & 1)) off |= (int64_t)1 << a.u_src[i];
+      tile[lds_index(tid + (it << 8))] = src[sbase + off];
+    }
   }
   __syncthreads();
-  for (int v = threadIdx.x; v < tvol; v += kPermThreads) {
-    int u = 0;
-    int64_t off = 0;
+  for (int it = 0; tid < tvol && it < iters; ++it) {
+    int u = u_lo;
+    int64_t off = w_lo;
 #pragma unroll
-    for (int i = 0; i < kPermMaxTile; ++i)
-      if (i < a.t) {
-        const int bit = (v >> i) & 1;
-        u |= bit << a.v_to_u[i];
-        off |= (int64_t)bit << a.v_dst[i];
+    for (int i = 8; i < kPermMaxTile; ++i)
+      if (i < t && ((it >> (i - 8)) & 1)) {
+        u |= 1 << a.v_to_u[i];
+        off |= (int64_t)1 << a.v_dst[i];
       }
     float2 x = tile[lds_index(u)];
     x.x *= a.scale;
     x.y *= a.scale * a.conj_sign;
     if (a.split) {
-      // hi plane at words [0, 2^b), lo plane at [2^b, 2^(b+1)) of this batch element
+      // hi plane at word idx, lo plane split_plane words further, in this batch element
       uint32_t* w = reinterpret_cast<uint32_t*>(dst);
+      int64_t idx = dbase + off;
+      if (a.split_ld)
+        idx = (idx >> a.split_kbits) * a.split_ld + (idx & (((int64_t)1 << a.split_kbits) - 1));
       const uint32_t hi = bf16_pair(x.x, x.y);
       const float hr = __uint_as_float(hi << 16), hiim = __uint_as_float(hi & 0xffff0000u);
-      w[dbase + off] = hi;
-      w[((int64_t)1 << a.nbits) + dbase + off] = bf16_pair(x.x - hr, x.y - hiim);
+      w[idx] = hi;
+      w[a.split_plane + idx] = bf16_pair(x.x - hr, x.y - hiim);
     } else {
       dst[dbase + off] = x;
     }
@@ -139,6 +161,9 @@ hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const 
   a.base_table = p.base_table;
   a.base_stride = p.base_stride;
   a.split = p.split;
+  a.split_kbits = p.split_kbits;
+  a.split_ld = p.split_ld;
+  a.split_plane = p.split_ld ? (((int64_t)1 << (b - p.split_kbits)) * p.split_ld) : ((int64_t)1 << b);
   const int64_t tiles = (int64_t)1 << no;
   const unsigned gx = (unsigned)std::min<int64_t>(tiles, 65536);
   const unsigned gy = (unsigned)(tiles / gx);

@@ -63,6 +63,11 @@ struct PermuteArgs {
   // split output: write bfloat16 hi = bf16(x) and lo = bf16(x - hi) of every complex number as
   // two planes of 2^nbits packed pairs (hi plane first) in the same 8 bytes per element
   int split = 0;
+  // split output with padded rows: destination index j goes to word (j >> split_kbits) * split_ld
+  // + (j & (2^split_kbits - 1)) of each plane, the lo plane 2^(nbits - split_kbits) * split_ld
+  // words after the hi plane (split_ld = 0: dense planes)
+  int split_kbits = 0;
+  int64_t split_ld = 0;
 };
 hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& a);
 
@@ -107,7 +112,7 @@ hipError_t launch_chain_counter(hipStream_t st, int64_t* chain0, int64_t value, 
 bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K);
 hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
                                  float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
-                                 const Renorm& rn = Renorm{});
+                                 const Renorm& rn = Renorm{}, int64_t lda = 0, int64_t ldb = 0);
 
 // Batched complex GEMM, C[m][n] = sum_k A[m][k] B[n][k].
 hipError_t launch_cgemm(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K,
@@ -123,7 +128,8 @@ enum {
   GEMM_SKINNY = 5,     // B in LDS, SIMT FP32 (N K <= 4096, K <= 64)
   GEMM_SPLITK = 6,     // one workgroup per output (M N <= 4096), SIMT FP32
   GEMM_SIMT = 7,       // one thread per output, SIMT FP32
-  GEMM_N_VARIANTS = 8
+  GEMM_TALL = 8,       // M large, N and K <= 64: B in LDS, A streamed into registers (HBM-bound)
+  GEMM_N_VARIANTS = 9
 };
 bool cgemm_variant_fits(int precision, int64_t M, int64_t N, int64_t K, int variant);
 int cgemm_default_variant(int precision, int64_t M, int64_t N, int64_t K);
@@ -135,6 +141,11 @@ hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, 
                            const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
                            const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn = Renorm{},
                            int variant = GEMM_AUTO, float2* scratch = nullptr, size_t scratch_bytes = 0);
+// Tall-skinny kernel (cgemm_tall.hip): powers of two, 8 <= N <= 64, 16 <= K <= 64.
+bool cgemm_tall_fits(int precision, int64_t M, int64_t N, int64_t K);
+hipError_t launch_cgemm_tall(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K, const float2* A,
+                             const float2* B, float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
+                             const uint32_t* amaxA, const uint32_t* amaxB, const Renorm& rn);
 // Bytes of scratch that lets an MFMA launch of this shape split K over more workgroups (0: the
 // launch fills the GPU without splitting, or its variant cannot split).
 size_t cgemm_split_scratch(int precision, int64_t M, int64_t N, int64_t K, int64_t batch, int variant = GEMM_AUTO);

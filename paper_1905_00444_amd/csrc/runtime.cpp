@@ -87,8 +87,25 @@ struct Operand {
   bool split = false;     // the permute writes split-BF16 planes for the pre-split GEMM
   std::vector<int> perm;  // dst bit i <- src bit perm[i]
   int nbits = 0;
+  int kbits = 0;          // contracted (lowest) bits, the GEMM's K
+  int64_t ld = 0;         // split planes: words between rows (0: dense, 2^kbits)
   size_t buf = 0;         // arena offset of the permuted copy
 };
+
+// Split operands with long rows get padded rows: rows 2^kbits words apart, a power of two of 32
+// KiB or more, fall into few L2 sets and the GEMM's tiles evict each other (3-5% slower measured
+// on K = 2^13 .. 2^15); 64 extra words (256 bytes) keep rows 256-byte aligned.
+constexpr int kSplitPadMinKbits = 13;
+constexpr int64_t kSplitPadWords = 64;
+
+// Row stride in words of a split operand's planes.
+static int64_t split_ld(const Operand& op) { return op.ld ? op.ld : ((int64_t)1 << op.kbits); }
+
+// Complex64 elements (8 bytes) of one chain's permuted copy of an operand.
+static size_t operand_elems(const Operand& op) {
+  if (op.split && op.ld) return ((size_t)1 << (op.nbits - op.kbits)) * (size_t)op.ld;
+  return (size_t)1 << op.nbits;
+}
 
 struct Step {
   int l = -1, r = -1;
@@ -562,6 +579,8 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
         if (!op->permute) p->permute_bytes += 16.0 * std::ldexp(1.0, op->nbits);
         op->permute = true;
         op->split = true;
+        op->kbits = (int)K.size();
+        if (op->kbits >= kSplitPadMinKbits) op->ld = ((int64_t)1 << op->kbits) + kSplitPadWords;
       }
     }
     st.flops = 8.0 * std::ldexp(1.0, st.m_bits + st.n_bits + st.k_bits);
@@ -612,8 +631,8 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     }
     if (nd.persistent) pers.push_back({bytes, 0, S, &nd.offset});
     else trans.push_back({bytes, i, (i == S - 1) ? S : nd.consumer, &nd.offset});
-    if (st.A.permute) trans.push_back({align_up(G * (sizeof(float2) << st.A.nbits)), i, i, &st.A.buf});
-    if (st.B.permute) trans.push_back({align_up(G * (sizeof(float2) << st.B.nbits)), i, i, &st.B.buf});
+    if (st.A.permute) trans.push_back({align_up(G * sizeof(float2) * operand_elems(st.A)), i, i, &st.A.buf});
+    if (st.B.permute) trans.push_back({align_up(G * sizeof(float2) * operand_elems(st.B)), i, i, &st.B.buf});
   }
   if (p->renorm) pers.push_back({align_up((n + S) * sizeof(NodeScale)), 0, S, &p->off_scales});
   if (p->gscratch_bytes) pers.push_back({align_up(p->gscratch_bytes), 0, S, &p->off_gscratch});
@@ -838,6 +857,8 @@ static qf_status run_operand(qf_plan* p, const Operand& op, const uint8_t* bits_
     src = wsp(c, nd.offset);
   }
   a.split = op.split ? 1 : 0;
+  a.split_kbits = op.kbits;
+  a.split_ld = op.split ? op.ld : 0;
   float2* dst = wsp(c, op.buf);
   QF_HIP(c, launch_permute(c->stream, src, dst, a));
   *ptr = dst;
@@ -940,7 +961,8 @@ static qf_status run_step(qf_plan* p, size_t i, const uint8_t* row, int64_t s) {
   }
   const Renorm rn = step_renorm(p, i);
   if (st.presplit) {
-    QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, 1, M * K, N * K, M * N, rn));
+    const int64_t lda = split_ld(st.A), ldb = split_ld(st.B);
+    QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, 1, M * lda, N * ldb, M * N, rn, lda, ldb));
   } else {
     e = plan_gemm(p, M, N, K, A, B, C, 1, rn);
     if (e != QF_OK) return e;
@@ -983,7 +1005,7 @@ static qf_status run_operand_batched(qf_plan* p, const Operand& op, const float2
   for (int i = 0; i < op.nbits; ++i) a.perm[i] = op.perm[i];
   a.scale = 1.0f;
   a.batch = p->G;
-  a.dst_bstride = (int64_t)1 << op.nbits;
+  a.dst_bstride = (int64_t)operand_elems(op);
   const float2* src;
   if (nd.leaf) {
     src = wsp(c, p->off_wl) + p->wl_qubits[nd.qubit].out_offset;
@@ -995,6 +1017,8 @@ static qf_status run_operand_batched(qf_plan* p, const Operand& op, const float2
     a.src_bstride = (int64_t)1 << nd.labels.size();
   }
   a.split = op.split ? 1 : 0;
+  a.split_kbits = op.kbits;
+  a.split_ld = op.split ? op.ld : 0;
   float2* dst = wsp(c, op.buf);
   QF_HIP(c, launch_permute(c->stream, src, dst, a));
   *ptr = dst;
@@ -1028,7 +1052,8 @@ static qf_status enqueue_group(qf_plan* p, const uint8_t* bits_dev, int64_t s_be
     }
     const Renorm rn = step_renorm(p, i);
     if (st.presplit) {
-      QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, G, M * K, N * K, M * N, rn));
+      const int64_t lda = split_ld(st.A), ldb = split_ld(st.B);
+      QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, G, M * lda, N * ldb, M * N, rn, lda, ldb));
     } else {
       e = plan_gemm(p, M, N, K, A, B, C, G, rn);
       if (e != QF_OK) return e;
@@ -1261,10 +1286,23 @@ qf_status qf_permute(qf_ctx* c, const void* src, void* dst, int nbits, const int
   return QF_OK;
 }
 
+// Names of the GEMM kernel variants (autotune files, error messages).
+static const char* const kVariantName[GEMM_N_VARIANTS] = {"auto",  "tiled4x4", "tiled2x2", "tiled1x2", "large",
+                                                          "skinny", "splitk",   "simt",     "tall"};
+
 qf_status qf_cgemm(qf_ctx* c, int precision, int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C,
                    int64_t batch, int64_t sa, int64_t sb, int64_t sc) {
+  return qf_cgemm_variant(c, precision, 0, M, N, K, A, B, C, batch, sa, sb, sc);
+}
+
+qf_status qf_cgemm_variant(qf_ctx* c, int precision, int variant, int64_t M, int64_t N, int64_t K, const void* A,
+                           const void* B, void* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc) {
   if (!c || !A || !B || !C || M < 1 || N < 1 || K < 1 || batch < 1 || precision < 0 || precision > 2)
     return fail(c, QF_ERR_ARG, "qf_cgemm: bad arguments");
+  if (variant < 0 || variant >= GEMM_N_VARIANTS) return fail(c, QF_ERR_ARG, "qf_cgemm_variant: unknown variant");
+  if (variant != GEMM_AUTO && !cgemm_variant_fits(precision, M, N, K, variant))
+    return fail(c, QF_ERR_UNSUPPORTED, std::string("qf_cgemm_variant: ") + kVariantName[variant] +
+                                           " does not fit this shape");
   const uint32_t *amA = nullptr, *amB = nullptr;
   if (precision == QF_FP16) {
     if (!c->ws || c->ws_bytes < kCtxScratch) return fail(c, QF_ERR_WORKSPACE, "qf_cgemm FP16 needs a workspace of 4 KiB");
@@ -1284,7 +1322,7 @@ qf_status qf_cgemm(qf_ctx* c, int precision, int64_t M, int64_t N, int64_t K, co
   }
   QF_HIP(c, launch_cgemm_ex(c->stream, precision, M, N, K, reinterpret_cast<const float2*>(A),
                             reinterpret_cast<const float2*>(B), reinterpret_cast<float2*>(C), batch, sa, sb, sc, amA, amB,
-                            Renorm{}, GEMM_AUTO, scratch, scratch_bytes));
+                            Renorm{}, variant, scratch, scratch_bytes));
   return QF_OK;
 }
 
@@ -1412,8 +1450,6 @@ qf_status qf_profile_read(qf_ctx* c, double* gemm_ms, int64_t* launches, double*
 }  // extern "C"
 
 // ---- autotuning ------------------------------------------------------------------------------
-static const char* const kVariantName[GEMM_N_VARIANTS] = {"auto",  "tiled4x4", "tiled2x2", "tiled1x2",
-                                                          "large", "skinny",   "splitk",   "simt"};
 
 static std::string device_tag(int dev) {
   hipDeviceProp_t pr;

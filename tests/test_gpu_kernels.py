@@ -196,3 +196,52 @@ def test_cgemm_presplit_matches_numpy(ctx, M, N, K):
     torch.cuda.synchronize()
     err = np.max(np.abs(Cg.cpu().numpy().astype(np.complex128) - ref) / bound)
     assert err <= TOL["bf16x3"], err
+
+
+TALL_SHAPES = [(64, 8, 16), (4096, 8, 16), (65536, 32, 32), (1 << 20, 32, 32), (8192, 64, 64), (16384, 16, 64),
+               (4096, 64, 16), (2048, 8, 64), (1 << 16, 64, 32)]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16"])
+@pytest.mark.parametrize("M,N,K", TALL_SHAPES)
+def test_cgemm_tall_matches_numpy(ctx, precision, M, N, K):
+    """The tall-skinny kernel (B in LDS, A streamed into registers), forced by name."""
+    import torch
+    from paper_1905_00444_amd import cgemm
+    _say(f"cgemm tall {precision} {M}x{N}x{K}")
+    rng = np.random.default_rng(M + 3 * N + 7 * K)
+    A = _rand_c64(rng, (M, K))
+    B = _rand_c64(rng, (N, K))
+    ref = A.astype(np.complex128) @ B.astype(np.complex128).T
+    bound = np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64).T
+    C = cgemm(ctx, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), precision, variant="tall")
+    torch.cuda.synchronize()
+    err = np.max(np.abs(C.cpu().numpy().astype(np.complex128) - ref) / bound)
+    assert err <= TOL[precision], err
+
+
+def test_cgemm_tall_batched_and_rejects_other_shapes(ctx):
+    import torch
+    import ctypes as Cc
+    from paper_1905_00444_amd import _lib, cgemm
+    _say("cgemm tall batched")
+    rng = np.random.default_rng(9)
+    Bt, M, N, K = 3, 4096, 32, 32
+    A = _rand_c64(rng, (Bt, M, K))
+    B = _rand_c64(rng, (Bt, N, K))
+    ref = np.einsum("bmk,bnk->bmn", A.astype(np.complex128), B.astype(np.complex128))
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.empty((Bt, M, N), dtype=torch.complex64, device="cuda")
+    st = ctx.lib.qf_cgemm_variant(ctx.h, 1, _lib.GEMM_VARIANTS.index("tall"), M, N, K, Cc.c_void_p(dA.data_ptr()),
+                                  Cc.c_void_p(dB.data_ptr()), Cc.c_void_p(dC.data_ptr()), Bt, M * K, N * K, M * N)
+    _lib.check(st, ctx.h)
+    torch.cuda.synchronize()
+    bound = np.einsum("bmk,bnk->bmn", np.abs(A).astype(np.float64), np.abs(B).astype(np.float64))
+    assert np.max(np.abs(dC.cpu().numpy() - ref) / bound) <= TOL["bf16x3"]
+    # K = 8 and N = 4 are below the kernel's operand tiles
+    with pytest.raises(RuntimeError):
+        cgemm(ctx, torch.zeros((4096, 8), dtype=torch.complex64, device="cuda"),
+              torch.zeros((32, 8), dtype=torch.complex64, device="cuda"), "bf16x3", variant="tall")
+    with pytest.raises(RuntimeError):
+        cgemm(ctx, torch.zeros((4096, 32), dtype=torch.complex64, device="cuda"),
+              torch.zeros((4, 32), dtype=torch.complex64, device="cuda"), "bf16x3", variant="tall")
