@@ -68,6 +68,29 @@ def test_permute_gather_with_fixed_bits(ctx, b, extra):
     assert np.array_equal(d.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("b", [1, 9, 16])
+def test_permute_on_8_byte_aligned_buffers(ctx, b):
+    """A source or destination offset by one complex64 (8-byte, not 16-byte, aligned): the
+    result still equals numpy's transpose."""
+    import torch
+    from paper_1905_00444_amd import permute
+    _say(f"permute 8-byte aligned b={b}")
+    rng = np.random.default_rng(200 + b)
+    x = _rand_c64(rng, 2 ** b)
+    axes = rng.permutation(b)
+    ref = np.transpose(x.reshape((2,) * b), axes).reshape(-1)
+    perm = [b - 1 - int(axes[b - 1 - i]) for i in range(b)]
+    big_s = torch.zeros(2 ** b + 1, dtype=torch.complex64, device="cuda")
+    big_d = torch.zeros(2 ** b + 1, dtype=torch.complex64, device="cuda")
+    big_s[1:] = torch.from_numpy(x).cuda()
+    for s, d in ((big_s[1:], big_d[1:]), (big_s[1:], big_d[:-1]), (big_s[:-1], big_d[1:])):
+        if s.data_ptr() != big_s[1:].data_ptr():
+            s.copy_(torch.from_numpy(x).cuda())
+        permute(ctx, s, d, perm)
+        torch.cuda.synchronize()
+        assert np.array_equal(d.cpu().numpy(), ref)
+
+
 SHAPES = [(1, 1, 1), (3, 5, 7), (16, 8, 4), (32, 32, 32), (64, 32, 64), (128, 64, 32), (256, 128, 512), (256, 128, 16),
           (1024, 64, 256), (512, 512, 2048), (2048, 1024, 128), (1, 1, 65536), (4, 8, 4096), (3, 2, 1000),
           (32768, 64, 8), (4096, 8, 16), (65536, 4, 4), (8192, 16, 64)]
