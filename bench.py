@@ -37,10 +37,10 @@ def parse():
                     help="skip timing the GEMM kernel variants of the plans' shapes before the warmup")
     ap.add_argument("--calib-copy", action="store_true",
                     help="launch one plain 1 GiB device copy first (HBM counter calibration)")
-    ap.add_argument("--workload", default="7x7-d40", choices=["7x7-d40", "8x9-d24", "6x6-d24-grad", "vendor-gemm"],
+    ap.add_argument("--workload", default="7x7-d40", choices=["7x7-d40", "8x9-d24", "6x6-d24-grad", "11x11-d24", "vendor-gemm"],
                     help="7x7-d40: the benchmark line (default); 8x9-d24: 70 qubits, batched chains through a "
                          "captured graph, beside the searched plan; 6x6-d24-grad: forward and backward of 64 "
-                         "amplitudes; vendor-gemm: the vendor real BF16 / FP32 GEMM on the same GPU (context for "
+                         "amplitudes; 11x11-d24: 121 qubits, a run of slices of the 64-slice region plan; vendor-gemm: the vendor real BF16 / FP32 GEMM on the same GPU (context for "
                          "the roofline: what the matrix cores sustain under the power limit)")
     return ap.parse_args()
 
@@ -157,6 +157,44 @@ def bench_6x6_grad(args):
     return 0
 
 
+def bench_11x11(args):
+    """121 qubits, 11x11 (1+24+1), bond 8: the region plan with two 3-bit corner cuts (64 slices,
+    peak 2^30), 8 amplitudes (3 open qubits) of one bitstring prefix, split-BF16 with the
+    renormalisation on (amplitudes are about 2^-60, below FP32's normal range).  Times a run of
+    consecutive slices and extrapolates to the 64-slice path sum."""
+    import torch
+    from paper_1905_00444_amd import Context, Circuit, Plan, autotune
+    from workloads.bitstrings import random_bitstrings
+    from workloads.circuits import generate
+    from workloads.plans import plan_11x11
+    circ = generate(11, 11, 24, 0)
+    plan, _ = plan_11x11(circ)
+    bits = random_bitstrings(1, 121, 1)
+    ctx = Context(0)
+    p = Plan(ctx, Circuit(ctx, circ.to_text()), plan, "bf16x3")
+    if not args.no_autotune:
+        autotune(p)
+    info = p.info()
+    n_slices = int(info["n_slices"])
+    S = min(max(args.steps, 1) * 2, n_slices)
+    out = p.amplitudes(bits, 0, 1)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = p.amplitudes(bits, 0, S)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fl = p.flops(0, S)  # executed: subtrees that no cut bit changes run once per call
+    full = p.flops(0, n_slices)
+    est = dt * full / fl  # the whole path sum at the measured rate
+    norm = float(torch.linalg.vector_norm(out).item())
+    print(json.dumps({"metric": "11x11 (1+24+1) amplitudes, split-BF16", "n_gpus": 1, "dtype": "bf16x3 (FP32 accumulate)",
+                      "slices_timed": S, "slices_per_amplitude": n_slices, "seconds": dt,
+                      "complex_tflops": fl / dt / 1e12, "flops_timed": fl, "flops_full_path_sum": full,
+                      "amplitudes_per_s_full_path_sum": 8 / est, "open_qubits": 3,
+                      "partial_amplitude_norm": norm, "data": "synthetic, seeded"}), flush=True)
+    return 0
+
+
 def sub_check(ctx):
     """Relative amplitude error against the FP64 state vector on a 4x4 (1+40+1) circuit
     (bond 32, as in the 7x7 workload), per precision."""
@@ -256,6 +294,8 @@ def main():
         return 2
     if args.workload == "8x9-d24":
         return bench_8x9(args)
+    if args.workload == "11x11-d24":
+        return bench_11x11(args)
     if args.workload == "6x6-d24-grad":
         return bench_6x6_grad(args)
     if args.workload == "vendor-gemm":
