@@ -202,3 +202,20 @@ def test_destroy_order_detaches_instead_of_dangling():
     lib.qf_ctx_destroy(ctx_a)
     lib.qf_circuit_destroy(ch)
     lib.qf_ctx_destroy(ctx_b)
+
+
+def test_cgemm_variant_argument_checks_without_device():
+    """qf_cgemm_variant refuses unknown variants and variants that do not fit the shape before
+    any device call (the pointers here are never dereferenced)."""
+    lib, ctx = _host_ctx()
+    p = C.c_void_p(256)
+    tall = _lib.GEMM_VARIANTS.index("tall")
+    assert lib.qf_cgemm_variant(ctx, 1, 99, 4096, 32, 32, p, p, p, 1, 0, 0, 0) == _lib.QF_ERR_ARG
+    assert lib.qf_cgemm_variant(ctx, 1, -1, 4096, 32, 32, p, p, p, 1, 0, 0, 0) == _lib.QF_ERR_ARG
+    # N = 4 and K = 8 are below the tall kernel's operand tiles; M = 100 is not a power of two
+    assert lib.qf_cgemm_variant(ctx, 1, tall, 4096, 4, 32, p, p, p, 1, 0, 0, 0) == _lib.QF_ERR_UNSUPPORTED
+    assert lib.qf_cgemm_variant(ctx, 1, tall, 4096, 32, 8, p, p, p, 1, 0, 0, 0) == _lib.QF_ERR_UNSUPPORTED
+    assert lib.qf_cgemm_variant(ctx, 1, tall, 100, 32, 32, p, p, p, 1, 0, 0, 0) == _lib.QF_ERR_UNSUPPORTED
+    assert lib.qf_cgemm_variant(ctx, 1, _lib.GEMM_VARIANTS.index("large"), 64, 64, 64, p, p, p, 1, 0, 0, 0) \
+        == _lib.QF_ERR_UNSUPPORTED
+    lib.qf_ctx_destroy(ctx)
