@@ -219,3 +219,12 @@ def test_cgemm_variant_argument_checks_without_device():
     assert lib.qf_cgemm_variant(ctx, 1, _lib.GEMM_VARIANTS.index("large"), 64, 64, 64, p, p, p, 1, 0, 0, 0) \
         == _lib.QF_ERR_UNSUPPORTED
     lib.qf_ctx_destroy(ctx)
+
+
+def test_single_qubit_circuit_is_refused():
+    """A one-qubit grid has no network to contract: the circuit is refused with a clear status."""
+    lib, ctx = _host_ctx()
+    st, ch = _circuit(lib, ctx, generate(1, 1, 8, 0))
+    assert st == _lib.QF_ERR_UNSUPPORTED
+    assert "2 qubits" in lib.qf_last_error(ctx).decode()
+    lib.qf_ctx_destroy(ctx)
