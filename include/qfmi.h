@@ -124,6 +124,20 @@ typedef struct {
                                   for FP32 and FP16, 0 for steps on the SIMT kernels */
 } qf_plan_info;
 
+/* One step of a laid-out plan (the TTGT roles the plan chose, Sec. III-E): operand A is the one
+ * with the larger free volume; C[M][N] = sum_K A[M][K] B[N][K]. */
+typedef struct {
+  int32_t lhs, rhs;           /* node ids as given in the plan description */
+  int32_t a_node, b_node;     /* the same two nodes in their A and B roles */
+  int32_t m_bits, n_bits, k_bits;
+  int32_t a_permuted, b_permuted; /* the operand is copied by a permute before the GEMM */
+  int32_t a_reordered, b_reordered; /* ... and that copy changes the element order (0: the copy
+                                       only fixes bits or splits into bfloat16 planes) */
+  int32_t presplit;           /* split-BF16 GEMM on operands split by their permutes */
+  int32_t persistent;         /* the result is kept across slices (no cut bit it depends on changes) */
+  double flops;               /* 8 * 2^(m+n+k) */
+} qf_step_info;
+
 typedef struct qf_ctx qf_ctx;
 typedef struct qf_circuit qf_circuit;
 typedef struct qf_plan qf_plan;
@@ -155,6 +169,8 @@ qf_status qf_plan_info_get(const qf_plan* plan, qf_plan_info* out);
  * for ONE bitstring over slices [s_begin, s_end), counting the reuse of steps whose inputs do
  * not change from one slice to the next (host only). */
 qf_status qf_plan_flops(const qf_plan* plan, int64_t s_begin, int64_t s_end, double* flops);
+/* Description of step i (0 <= i < n_steps) of a laid-out plan (host only). */
+qf_status qf_plan_step_info(const qf_plan* plan, int i, qf_step_info* out);
 void qf_plan_destroy(qf_plan* plan);
 
 /* Amplitudes for n_batch bitstrings over slices [s_begin, s_end) (paper Sec. III-A: the

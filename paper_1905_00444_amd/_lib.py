@@ -46,6 +46,14 @@ class qf_plan_info(C.Structure):
                 ("mfma_flops_per_slice", C.c_double)]
 
 
+class qf_step_info(C.Structure):
+    _fields_ = [("lhs", C.c_int32), ("rhs", C.c_int32), ("a_node", C.c_int32), ("b_node", C.c_int32),
+                ("m_bits", C.c_int32), ("n_bits", C.c_int32), ("k_bits", C.c_int32),
+                ("a_permuted", C.c_int32), ("b_permuted", C.c_int32), ("a_reordered", C.c_int32),
+                ("b_reordered", C.c_int32), ("presplit", C.c_int32), ("persistent", C.c_int32),
+                ("flops", C.c_double)]
+
+
 EXPORTS = {
     "qf_ctx_create": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
     "qf_ctx_set_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
@@ -56,6 +64,7 @@ EXPORTS = {
                                     C.POINTER(C.c_void_p)]),
     "qf_circuit_set_values": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
     "qf_circuit_destroy": (None, [C.c_void_p]),
+    "qf_plan_step_info": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(qf_step_info)]),
     "qf_plan_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(qf_plan_desc), C.POINTER(C.c_void_p)]),
     "qf_plan_info_get": (C.c_int, [C.c_void_p, C.POINTER(qf_plan_info)]),
     "qf_plan_destroy": (None, [C.c_void_p]),

@@ -170,6 +170,15 @@ class Plan:
         check(self.ctx.lib.qf_plan_info_get(self.h, C.byref(inf)), self.ctx.h)
         return {k: getattr(inf, k) for k, _ in _lib.qf_plan_info._fields_}
 
+    def steps(self) -> list:
+        """Per-step layout the plan chose (TTGT roles, GEMM sizes, which operands are copied)."""
+        out = []
+        for i in range(self.info()["n_steps"]):
+            si = _lib.qf_step_info()
+            check(self.ctx.lib.qf_plan_step_info(self.h, i, C.byref(si)), self.ctx.h)
+            out.append({k: getattr(si, k) for k, _ in _lib.qf_step_info._fields_})
+        return out
+
     def flops(self, s_begin: int, s_end: int) -> float:
         """Executed algorithmic flops for one bitstring over slices [s_begin, s_end)."""
         f = C.c_double()

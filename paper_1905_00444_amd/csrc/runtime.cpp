@@ -749,6 +749,35 @@ qf_status qf_plan_flops(const qf_plan* p, int64_t s_begin, int64_t s_end, double
   return QF_OK;
 }
 
+// A permute whose source positions increase with the destination bit keeps the element order:
+// it only fixes bits (a slice, a bitstring's output bit) or splits into bfloat16 planes.
+static bool order_preserving(const std::vector<int>& perm) {
+  for (size_t i = 1; i < perm.size(); ++i)
+    if (perm[i] <= perm[i - 1]) return false;
+  return true;
+}
+
+qf_status qf_plan_step_info(const qf_plan* p, int i, qf_step_info* out) {
+  if (!p || !out || i < 0 || i >= (int)p->steps.size()) return QF_ERR_ARG;
+  const Step& st = p->steps[i];
+  std::memset(out, 0, sizeof(*out));
+  out->lhs = st.l;
+  out->rhs = st.r;
+  out->a_node = st.A.node;
+  out->b_node = st.B.node;
+  out->m_bits = st.m_bits;
+  out->n_bits = st.n_bits;
+  out->k_bits = st.k_bits;
+  out->a_permuted = st.A.permute;
+  out->b_permuted = st.B.permute;
+  out->a_reordered = st.A.permute && !order_preserving(st.A.perm);
+  out->b_reordered = st.B.permute && !order_preserving(st.B.perm);
+  out->presplit = st.presplit;
+  out->persistent = p->nodes[p->n + i].persistent;
+  out->flops = st.flops;
+  return QF_OK;
+}
+
 qf_status qf_plan_info_get(const qf_plan* p, qf_plan_info* out) {
   if (!p || !out) return QF_ERR_ARG;
   std::memset(out, 0, sizeof(*out));

@@ -228,3 +228,43 @@ def test_single_qubit_circuit_is_refused():
     assert st == _lib.QF_ERR_UNSUPPORTED
     assert "2 qubits" in lib.qf_last_error(ctx).decode()
     lib.qf_ctx_destroy(ctx)
+
+
+def test_plan_step_info_is_consistent_with_the_plan():
+    """Per-step layout of the 7x7 (1+40+1) split-BF16 plan: sizes multiply to the step flops, the
+    flops add up to the plan's, every leaf operand is gathered, the big steps run pre-split."""
+    lib, ctx = _host_ctx()
+    c = generate(7, 7, 40, 0)
+    plan, _ = plan_7x7(c, 40)
+    st, ch = _circuit(lib, ctx, c)
+    st, ph = _plan(lib, ctx, ch, plan, precision=1)
+    assert st == 0
+    inf = _lib.qf_plan_info()
+    assert lib.qf_plan_info_get(ph, C.byref(inf)) == 0
+    n = inf.n_qubits
+    steps = np.asarray(plan["steps"]).reshape(-1, 2)
+    total = 0.0
+    for i in range(inf.n_steps):
+        si = _lib.qf_step_info()
+        assert lib.qf_plan_step_info(ph, i, C.byref(si)) == 0
+        assert (si.lhs, si.rhs) == tuple(int(x) for x in steps[i])
+        assert {si.a_node, si.b_node} == {si.lhs, si.rhs}
+        assert si.m_bits >= si.n_bits  # A has the larger free volume
+        assert si.flops == 8.0 * 2.0 ** (si.m_bits + si.n_bits + si.k_bits)
+        for node, permuted, reordered in ((si.a_node, si.a_permuted, si.a_reordered),
+                                          (si.b_node, si.b_permuted, si.b_reordered)):
+            if node < n:
+                assert permuted  # world-line slices are gathered
+            assert permuted or not reordered
+        fits = si.m_bits >= 8 and si.n_bits >= 7 and si.k_bits >= 4
+        assert si.presplit == fits
+        if si.presplit:
+            assert si.a_permuted and si.b_permuted  # the split happens in the permute
+        total += si.flops
+    assert total == pytest.approx(inf.flops_per_slice, rel=1e-12)
+    si = _lib.qf_step_info()
+    assert lib.qf_plan_step_info(ph, inf.n_steps, C.byref(si)) == _lib.QF_ERR_ARG
+    assert lib.qf_plan_step_info(ph, -1, C.byref(si)) == _lib.QF_ERR_ARG
+    lib.qf_plan_destroy(ph)
+    lib.qf_circuit_destroy(ch)
+    lib.qf_ctx_destroy(ctx)
