@@ -254,6 +254,24 @@ def test_7x7_d32_random_slice_vs_tensor_network_oracle(ctx):
         assert rel_err(got, ref) <= bound, prec
 
 
+def test_7x7_d40_random_slice_precisions_agree(ctx):
+    """The benchmark's random 7x7 (1+40+1) circuit at full size (peak 2^30): one nonvanishing
+    slice of one prefix (64 amplitudes) in split-BF16 and FP16 against FP32 on the same slice.
+    No FP64 reference reaches this size in a test (one slice is 7.5e14 flop); FP32 itself is
+    pinned to the FP64 oracles on the 7x7 (1+32+1) slice above and on the 4x4 (1+40+1) circuit
+    (bond 32, as here) of the benchmark's sub-check."""
+    _say("7x7 d40 random slice, split-BF16 and FP16 vs FP32")
+    c = generate(7, 7, 40, 0)
+    plan, _ = plan_7x7(c, 40)
+    bits = random_bitstrings(1, 49, 1)
+    s = nonvanishing_slices(c, plan, bits[0], 1)[0]
+    ref = _amps(ctx, c, plan, bits, "fp32", s, s + 1)
+    assert np.linalg.norm(ref) > 1e-20
+    for prec, bound in (("bf16x3", 1e-4), ("fp16", 5e-3)):
+        got = _amps(ctx, c, plan, bits, prec, s, s + 1)
+        assert rel_err(got, ref) <= bound, prec
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_renormalisation_is_exact(ctx, precision):
     """Power-of-two renormalisation only moves exponents: FP32 and split-BF16 results with and
