@@ -118,9 +118,10 @@ class _Order:
 class CostModel:
     """Time of one contraction step on one GPU (seconds)."""
     precision: str = "bf16x3"
-    gemm_rate: Dict[str, float] = field(default_factory=lambda: {"fp32": 124e12, "bf16x3": 447e12,
-                                                                 "fp16": 618e12})
-    bandwidth: float = 5.0e12       # bytes/s reached by the permutes
+    # large-GEMM rates and permute bandwidth measured on one MI355X (complex flop/s, bytes/s)
+    gemm_rate: Dict[str, float] = field(default_factory=lambda: {"fp32": 137e12, "bf16x3": 520e12,
+                                                                 "fp16": 750e12})
+    bandwidth: float = 5.3e12       # bytes/s reached by the permutes
     launch: float = 4e-6            # seconds per kernel launch
     batch: int = 1                  # chains per launch
     measured: Dict[Tuple[int, int, int], float] = field(default_factory=dict)  # (M, N, K) bits -> s
