@@ -150,9 +150,22 @@ def bench_6x6_grad(args):
     t2 = time.perf_counter()
     fwd, bwd = (t1 - t0) / args.steps, (t2 - t1) / args.steps
     fl = 64 * p.info()["flops_per_slice"]
+    # the same forward with all 64 bitstrings as chains of one batched launch sequence
+    pb = Plan(ctx, Circuit(ctx, circ.to_text()), plan, "fp32", batch=64)
+    bits_t = torch.from_numpy(bits).to(ctx.device)
+    ab = pb.amplitudes(bits_t)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(args.steps):
+        ab = pb.amplitudes(bits_t)
+    torch.cuda.synchronize()
+    fwd_b = (time.perf_counter() - t3) / args.steps
+    diff = float((torch.linalg.vector_norm(ab - a) / torch.linalg.vector_norm(a)).item())
     print(json.dumps({"metric": "6x6 (1+24+1) forward and backward, 64 bitstrings", "n_gpus": 1, "dtype": "fp32",
                       "forward_s": fwd, "backward_s": bwd, "forward_amplitudes_per_s": 64 / fwd,
                       "forward_complex_tflops": fl / fwd / 1e12, "backward_over_forward": bwd / fwd,
+                      "forward_batched_s": fwd_b, "forward_batched_amplitudes_per_s": 64 / fwd_b,
+                      "forward_batched_rel_diff": diff,
                       "gates": int(g.shape[0]), "data": "synthetic, seeded"}), flush=True)
     return 0
 
