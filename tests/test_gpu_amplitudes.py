@@ -241,7 +241,7 @@ def test_product_circuit_7x7_d40_bench_launch_configuration(ctx):
 
 def test_7x7_d32_random_slice_vs_tensor_network_oracle(ctx):
     """A random 7x7 (1+32+1) circuit (bond 16, peak 2^28): one slice of one prefix (64
-    amplitudes) against the FP64 tensor-network oracle, FP32 and split-BF16."""
+    amplitudes) against the FP64 tensor-network oracle, in all three precisions."""
     _say("7x7 d32 random slice vs oracle-TN")
     c = generate(7, 7, 32, 0)
     plan, _ = plan_7x7(c, 32)
@@ -249,7 +249,7 @@ def test_7x7_d32_random_slice_vs_tensor_network_oracle(ctx):
     s = nonvanishing_slices(c, plan, bits[0], 4)[-1]
     ref = tn.amplitudes(c.to_text(), bits, plan, slices=[s])
     assert np.linalg.norm(ref) > 1e-20
-    for prec, bound in (("fp32", 1e-5), ("bf16x3", 1e-4)):
+    for prec, bound in (("fp32", 1e-5), ("bf16x3", 1e-4), ("fp16", 5e-3)):
         got = _amps(ctx, c, plan, bits, prec, s, s + 1)
         assert rel_err(got, ref) <= bound, prec
 
@@ -270,6 +270,21 @@ def test_7x7_d40_random_slice_precisions_agree(ctx):
     for prec, bound in (("bf16x3", 1e-4), ("fp16", 5e-3)):
         got = _amps(ctx, c, plan, bits, prec, s, s + 1)
         assert rel_err(got, ref) <= bound, prec
+
+
+def test_11x11_d24_random_slice_precisions_agree(ctx):
+    """The 121-qubit random circuit (peak 2^30, 120 contractions; amplitudes about 2^-60, kept in
+    range by the renormalisation): one slice of one prefix in split-BF16 against FP32.  The bound
+    is the split-BF16 drift reading, n 2^-16 for n contractions."""
+    _say("11x11 d24 random slice, split-BF16 vs FP32")
+    c = generate(11, 11, 24, 0)
+    plan, _ = plan_11x11(c)
+    bits = random_bitstrings(1, 121, 1)
+    s = nonvanishing_slices(c, plan, bits[0], 1)[0]
+    ref = _amps(ctx, c, plan, bits, "fp32", s, s + 1)
+    assert np.linalg.norm(ref) > 0
+    got = _amps(ctx, c, plan, bits, "bf16x3", s, s + 1)
+    assert rel_err(got, ref) <= len(plan["steps"]) * 2.0 ** -16
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
