@@ -161,11 +161,22 @@ def bench_6x6_grad(args):
     torch.cuda.synchronize()
     fwd_b = (time.perf_counter() - t3) / args.steps
     diff = float((torch.linalg.vector_norm(ab - a) / torch.linalg.vector_norm(a)).item())
+    # and the backward with the 64 chains per launch
+    pg = Plan(ctx, Circuit(ctx, circ.to_text()), plan, "fp32", backward=True, batch=64)
+    gb = pg.backward(bits_t, 2 * a)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(args.steps):
+        gb = pg.backward(bits_t, 2 * a)
+    torch.cuda.synchronize()
+    bwd_b = (time.perf_counter() - t4) / args.steps
+    gdiff = float((torch.linalg.vector_norm(gb - g) / torch.linalg.vector_norm(g)).item())
     print(json.dumps({"metric": "6x6 (1+24+1) forward and backward, 64 bitstrings", "n_gpus": 1, "dtype": "fp32",
                       "forward_s": fwd, "backward_s": bwd, "forward_amplitudes_per_s": 64 / fwd,
                       "forward_complex_tflops": fl / fwd / 1e12, "backward_over_forward": bwd / fwd,
                       "forward_batched_s": fwd_b, "forward_batched_amplitudes_per_s": 64 / fwd_b,
-                      "forward_batched_rel_diff": diff,
+                      "forward_batched_rel_diff": diff, "backward_batched_s": bwd_b,
+                      "backward_batched_rel_diff": gdiff,
                       "gates": int(g.shape[0]), "data": "synthetic, seeded"}), flush=True)
     return 0
 

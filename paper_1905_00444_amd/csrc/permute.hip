@@ -213,6 +213,43 @@ scatter_add_kernel(const float2* __restrict__ src, float2* __restrict__ dst, Sca
   }
 }
 
+// Batched adjoint of the leaf gathers: chain g adds its 2^nbits values src[g][j] at
+// dst[base_table[g * base_stride] + sum_i bit_i(j) << perm[i]].  Chains that fixed the same bits
+// add into the same entries, so the additions are atomic (the order of the chains' terms in a
+// sum is therefore not fixed).  Chains with chain_b[g] < 0 (past the end) add nothing.
+__global__ void __launch_bounds__(256)
+scatter_add_batched_kernel(const float2* __restrict__ src, float2* __restrict__ dst, ScatterArgs a,
+                           const int64_t* __restrict__ base_table, int base_stride, int64_t src_bstride,
+                           const int32_t* __restrict__ chain_b) {
+  const int g = blockIdx.y;
+  if (chain_b[g] < 0) return;
+  const int64_t n = (int64_t)1 << a.nbits;
+  const int64_t base = a.base + base_table[(int64_t)g * base_stride];
+  src += (int64_t)g * src_bstride;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    int64_t off = base;
+    for (int i = 0; i < a.nbits; ++i) off |= ((j >> i) & 1) << a.perm[i];
+    const float2 v = src[j];
+    float* d = reinterpret_cast<float*>(dst + off);
+    atomicAdd(d, v.x);
+    atomicAdd(d + 1, v.y);
+  }
+}
+
+hipError_t launch_scatter_add_batched(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& p, int G,
+                                      const int64_t* base_table, int base_stride, int64_t src_bstride,
+                                      const int32_t* chain_b) {
+  ScatterArgs a = {};
+  a.nbits = p.nbits;
+  for (int i = 0; i < p.nbits; ++i) a.perm[i] = p.perm[i];
+  a.base = p.src_base;
+  const int64_t n = (int64_t)1 << p.nbits;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(scatter_add_batched_kernel, dim3(blocks, (unsigned)G), dim3(256), 0, st, src, dst, a, base_table,
+                     base_stride, src_bstride, chain_b);
+  return hipGetLastError();
+}
+
 hipError_t launch_scatter_add(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& p) {
   ScatterArgs a = {};
   a.nbits = p.nbits;

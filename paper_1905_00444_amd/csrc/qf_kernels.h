@@ -73,6 +73,11 @@ hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const 
 
 // Adjoint of the gather: dst[src_base + sum_i bit_i(j) << perm[i]] += src[j] (same args).
 hipError_t launch_scatter_add(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& a);
+// Batched over G chains: chain g's source at src + g * src_bstride, its extra base offset
+// base_table[g * base_stride] (added to a.src_base); atomic additions; chains with chain_b < 0 skip.
+hipError_t launch_scatter_add_batched(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& a, int G,
+                                      const int64_t* base_table, int base_stride, int64_t src_bstride,
+                                      const int32_t* chain_b);
 
 // Gradients of every gate from the world-line environments env (same layout as the
 // world-lines): grad[out][e] += sum over tensor elements (complex64, 4 entries per gate).
@@ -81,6 +86,9 @@ hipError_t launch_worldline_grad(hipStream_t st, const WlQubit* qubits, int n_qu
 
 // env_root[sum_t bit_t(j) << pos[t]] = cot[j] (complex128 -> complex64), j < 2^k.
 hipError_t launch_seed_root(hipStream_t st, const double2* cot, int k, const int* pos, float2* env_root);
+// Batched: env_root + g 2^k gets chain g's cotangent row cot + chain_b[g] 2^k (zeros if chain_b < 0).
+hipError_t launch_seed_root_batched(hipStream_t st, const double2* cot, int k, const int* pos, int G,
+                                    const int32_t* chain_b, float2* env_root);
 
 hipError_t launch_zero(hipStream_t st, void* p, size_t bytes);
 

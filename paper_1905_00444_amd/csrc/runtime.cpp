@@ -333,7 +333,8 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   if (p->backward) p->flags |= QF_PLAN_NO_HOIST;
   p->G = d->batch > 1 ? d->batch : 1;
   if (p->G & (p->G - 1)) return fail(ctx, QF_ERR_ARG, "batch must be a power of two");
-  if (p->G > 1 && p->backward) return fail(ctx, QF_ERR_UNSUPPORTED, "backward plans run chains one at a time");
+  if (p->G > 1 && p->backward && (d->flags & QF_PLAN_GRAPH))
+    return fail(ctx, QF_ERR_UNSUPPORTED, "backward plans are not captured in a graph");
   if (p->G > 1) p->flags |= QF_PLAN_NO_HOIST;
   p->graph = p->G > 1 && (d->flags & QF_PLAN_GRAPH);
   p->renorm = !p->backward && !(d->flags & QF_PLAN_NO_RENORM);
@@ -597,8 +598,8 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
       const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
       if (!st.presplit) need = std::max(need, cgemm_split_scratch(p->precision, M, N, K, p->G));
       if (p->backward) {
-        need = std::max(need, cgemm_split_scratch(p->precision, M, K, N, 1));
-        need = std::max(need, cgemm_split_scratch(p->precision, N, K, M, 1));
+        need = std::max(need, cgemm_split_scratch(p->precision, M, K, N, p->G));
+        need = std::max(need, cgemm_split_scratch(p->precision, N, K, M, p->G));
       }
     }
     p->gscratch_bytes = need;
@@ -625,8 +626,8 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
       // every forward tensor is kept for the reverse sweep, next to its environment
       pers.push_back({bytes, 0, S, &nd.offset});
       pers.push_back({bytes, 0, S, &nd.env});
-      if (st.A.permute) pers.push_back({align_up(sizeof(float2) << st.A.nbits), 0, S, &st.A.buf});
-      if (st.B.permute) pers.push_back({align_up(sizeof(float2) << st.B.nbits), 0, S, &st.B.buf});
+      if (st.A.permute) pers.push_back({align_up(G * (sizeof(float2) << st.A.nbits)), 0, S, &st.A.buf});
+      if (st.B.permute) pers.push_back({align_up(G * (sizeof(float2) << st.B.nbits)), 0, S, &st.B.buf});
       continue;
     }
     if (nd.persistent) pers.push_back({bytes, 0, S, &nd.offset});
@@ -651,11 +652,12 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
       max_a = std::max(max_a, va);
       max_b = std::max(max_b, vb);
     }
+    const size_t G = (size_t)p->G;  // per chain in batched backward plans
     pers.push_back({align_up(wl_elems * sizeof(float2)), 0, S, &p->off_envwl});
-    pers.push_back({align_up(max_q), 0, S, &p->off_bq});
-    pers.push_back({align_up(max_c), 0, S, &p->off_bp});
-    pers.push_back({align_up(max_a), 0, S, &p->off_bea});
-    pers.push_back({align_up(max_b), 0, S, &p->off_beb});
+    pers.push_back({align_up(G * max_q), 0, S, &p->off_bq});
+    pers.push_back({align_up(G * max_c), 0, S, &p->off_bp});
+    pers.push_back({align_up(G * max_a), 0, S, &p->off_bea});
+    pers.push_back({align_up(G * max_b), 0, S, &p->off_beb});
   }
   for (auto& b : pers) { *b.where = cur; cur = align_up(cur + b.bytes); }
   const size_t tbase = cur;
@@ -1228,6 +1230,98 @@ static qf_status route_env(qf_plan* p, const Operand& op, const float2* E, const
   return QF_OK;
 }
 
+// ---- batched backward: G chains (bitstring x slice pairs) through every forward and reverse step
+// as one batched launch each; leaf environments of all chains add atomically into the shared
+// world-line environments.
+static qf_status batched_transpose(qf_plan* p, int xb, int yb, int conj, const float2* src, float2* dst) {
+  PermuteArgs a;
+  transpose_args(xb, yb, conj, &a);
+  a.batch = p->G;
+  a.src_bstride = a.dst_bstride = (int64_t)1 << (xb + yb);
+  QF_HIP(p->ctx, launch_permute(p->ctx->stream, src, dst, a));
+  return QF_OK;
+}
+
+static qf_status route_env_batched(qf_plan* p, const Operand& op, const float2* E) {
+  qf_ctx* c = p->ctx;
+  const Node& nd = p->nodes[op.node];
+  const int32_t* chain_b = reinterpret_cast<const int32_t*>(c->ws + p->off_chainb);
+  PermuteArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nbits = op.nbits;
+  a.scale = 1.0f;
+  if (nd.leaf) {
+    for (int i = 0; i < op.nbits; ++i) a.perm[i] = op.perm[i];
+    float2* dst = wsp(c, p->off_envwl) + p->wl_qubits[nd.qubit].out_offset;
+    const int64_t* btab = reinterpret_cast<const int64_t*>(c->ws + p->off_btable) + nd.qubit;
+    QF_HIP(c, launch_scatter_add_batched(c->stream, E, dst, a, p->G, btab, p->n, (int64_t)1 << op.nbits, chain_b));
+    return QF_OK;
+  }
+  if (op.permute) {
+    for (int i = 0; i < op.nbits; ++i) a.perm[op.perm[i]] = i;  // inverse permutation
+  } else {
+    for (int i = 0; i < op.nbits; ++i) a.perm[i] = i;
+  }
+  a.batch = p->G;
+  a.src_bstride = a.dst_bstride = (int64_t)1 << op.nbits;
+  QF_HIP(c, launch_permute(c->stream, E, wsp(c, nd.env), a));
+  return QF_OK;
+}
+
+static qf_status backward_group(qf_plan* p, const uint8_t* bits_dev, const double* cot_dev, int64_t s_begin,
+                                int64_t s_range, int64_t n_chains) {
+  qf_ctx* c = p->ctx;
+  const int n = p->n, G = p->G, k = (int)p->open.size();
+  int64_t* chain0 = reinterpret_cast<int64_t*>(c->ws + 8);
+  int32_t* chain_b = reinterpret_cast<int32_t*>(c->ws + p->off_chainb);
+  QF_HIP(c, launch_chain_setup(c->stream, chain0, G, n, reinterpret_cast<const LeafDesc*>(c->ws + p->off_leafdesc),
+                               bits_dev, n, s_begin, s_range, n_chains,
+                               reinterpret_cast<int64_t*>(c->ws + p->off_btable), chain_b));
+  // forward, every tensor of every chain kept
+  for (size_t i = 0; i < p->steps.size(); ++i) {
+    const Step& st = p->steps[i];
+    const float2 *A, *B;
+    qf_status e = run_operand_batched(p, st.A, &A);
+    if (e != QF_OK) return e;
+    e = run_operand_batched(p, st.B, &B);
+    if (e != QF_OK) return e;
+    const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+    e = plan_gemm(p, M, N, K, A, B, wsp(c, p->nodes[n + i].offset), G);
+    if (e != QF_OK) return e;
+  }
+  const Node& root = p->nodes.back();
+  QF_HIP(c, launch_seed_root_batched(c->stream, reinterpret_cast<const double2*>(cot_dev), k, p->root_pos.data(), G,
+                                     chain_b, wsp(c, root.env)));
+  float2* Q = wsp(c, p->off_bq);
+  float2* P = wsp(c, p->off_bp);
+  float2* EA = wsp(c, p->off_bea);
+  float2* EB = wsp(c, p->off_beb);
+  for (int i = (int)p->steps.size() - 1; i >= 0; --i) {
+    const Step& st = p->steps[i];
+    const float2* envC = wsp(c, p->nodes[n + i].env);
+    const float2* Aop = wsp(c, st.A.permute ? st.A.buf : p->nodes[st.A.node].offset);
+    const float2* Bop = wsp(c, st.B.permute ? st.B.buf : p->nodes[st.B.node].offset);
+    const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+    // env(A)[m][k] = sum_n env(C)[m][n] conj(B[n][k]); env(B)[n][k] = sum_m env(C)[m][n] conj(A[m][k])
+    qf_status e = batched_transpose(p, st.n_bits, st.k_bits, 1, Bop, Q);
+    if (e != QF_OK) return e;
+    e = plan_gemm(p, M, K, N, envC, Q, EA, G);
+    if (e != QF_OK) return e;
+    e = batched_transpose(p, st.m_bits, st.n_bits, 0, envC, P);
+    if (e != QF_OK) return e;
+    e = batched_transpose(p, st.m_bits, st.k_bits, 1, Aop, Q);
+    if (e != QF_OK) return e;
+    e = plan_gemm(p, N, K, M, P, Q, EB, G);
+    if (e != QF_OK) return e;
+    e = route_env_batched(p, st.A, EA);
+    if (e != QF_OK) return e;
+    e = route_env_batched(p, st.B, EB);
+    if (e != QF_OK) return e;
+  }
+  QF_HIP(c, launch_chain_counter(c->stream, chain0, G, 1));
+  return QF_OK;
+}
+
 extern "C" qf_status qf_backward(qf_plan* p, int n_batch, const uint8_t* bits_dev, const double* cot_dev,
                                  int64_t s_begin, int64_t s_end, float* grad_dev) {
   if (!p || !p->ctx || !p->circ) return QF_ERR_ARG;
@@ -1246,6 +1340,20 @@ extern "C" qf_status qf_backward(qf_plan* p, int n_batch, const uint8_t* bits_de
   const int n = p->n;
   const int k = (int)p->open.size();
   const int S_steps = (int)p->steps.size();
+  if (p->G > 1) {
+    const int64_t s_range = s_end - s_begin;
+    const int64_t n_chains = (int64_t)n_batch * s_range;
+    QF_HIP(c, launch_chain_counter(c->stream, reinterpret_cast<int64_t*>(c->ws + 8), 0, 0));
+    for (int64_t g = 0; g < (n_chains + p->G - 1) / p->G; ++g) {
+      e = backward_group(p, bits_dev, cot_dev, s_begin, s_range, n_chains);
+      if (e != QF_OK) return e;
+    }
+    QF_HIP(c, launch_worldline_grad(c->stream, reinterpret_cast<const WlQubit*>(c->ws + p->off_wlq), n, p->max_nbond,
+                                    reinterpret_cast<const WlInstr*>(c->ws + p->off_prog),
+                                    reinterpret_cast<const float2*>(c->ws + p->off_gates), wsp(c, p->off_envwl),
+                                    reinterpret_cast<float2*>(grad_dev)));
+    return QF_OK;
+  }
   float2* Q = wsp(c, p->off_bq);
   float2* P = wsp(c, p->off_bp);
   float2* EA = wsp(c, p->off_bea);

@@ -228,6 +228,37 @@ hipError_t launch_seed_root(hipStream_t st, const double2* cot, int k, const int
   return hipGetLastError();
 }
 
+// Batched: env_root[g][...] = cot[chain_b[g]][j], zero for chains past the end (chain_b < 0).
+__global__ void __launch_bounds__(256)
+seed_root_batched_kernel(const double2* __restrict__ cot, AccArgs a, const int32_t* __restrict__ chain_b,
+                         float2* __restrict__ env_root) {
+  const int64_t n = (int64_t)1 << a.k;
+  const int g = blockIdx.y;
+  const int32_t b = chain_b[g];
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    int64_t dst = 0;
+    for (int t = 0; t < a.k; ++t) dst |= ((j >> t) & 1) << a.pos[t];
+    float2 v = make_float2(0.f, 0.f);
+    if (b >= 0) {
+      const double2 c = cot[((int64_t)b << a.k) + j];
+      v = make_float2((float)c.x, (float)c.y);
+    }
+    env_root[(int64_t)g * n + dst] = v;
+  }
+}
+
+hipError_t launch_seed_root_batched(hipStream_t st, const double2* cot, int k, const int* pos, int G,
+                                    const int32_t* chain_b, float2* env_root) {
+  AccArgs a;
+  a.k = k;
+  for (int t = 0; t < 32; ++t) a.pos[t] = t < k ? pos[t] : 0;
+  const int64_t n = (int64_t)1 << k;
+  unsigned blocks = (unsigned)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(seed_root_batched_kernel, dim3(blocks, (unsigned)G), dim3(256), 0, st, cot, a, chain_b, env_root);
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256) zero_kernel(uint4* __restrict__ p, int64_t n16) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = make_uint4(0u, 0u, 0u, 0u);

@@ -138,3 +138,49 @@ def test_autograd_function_matches_direct_backward(ctx):
     fb, fc = _expand_open(bits, [11], 2 * amps.detach().cpu().numpy())
     ref = _oracle_grad(text, fb, fc)
     assert rel_err(vals.grad.cpu().numpy(), ref) <= 1e-4
+
+
+@pytest.mark.parametrize("G", [4, 8])
+def test_batched_backward_matches_sequential_and_oracle(ctx, G):
+    """Backward with G chains per launch (chains = bitstrings x slices, 3 x 8 here): equal to the
+    one-chain-at-a-time backward up to the order in which chains add into the world-line
+    environments (atomic additions), and to the FP64 adjoint oracle.  Cuts and open qubits as in
+    the test above."""
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    _say(f"batched backward G={G}")
+    c = generate(4, 5, 32, 2)
+    text = c.to_text()
+    qid = c.qubit_of()
+    cuts = [[qid[(1, 3)], qid[(2, 3)], 0, 2], [qid[(3, 1)], qid[(3, 2)], 1, 1]]
+    plan, _ = region_plan(c, 2, 2, cuts, [(3, 4), (2, 4)])
+    bits = random_bitstrings(3, 20, 7)
+    rng = np.random.default_rng(3)
+    cot = rng.normal(size=(3, 4)) + 1j * rng.normal(size=(3, 4))
+    seq = Plan(ctx, Circuit(ctx, text), plan, "fp32", backward=True).backward(bits, cot)
+    bat = Plan(ctx, Circuit(ctx, text), plan, "fp32", backward=True, batch=G).backward(bits, cot)
+    torch.cuda.synchronize()
+    seq, bat = seq.cpu().numpy(), bat.cpu().numpy()
+    assert rel_err(bat, seq) <= 1e-5
+    fb, fc = _expand_open(bits, plan["open"], cot)
+    assert rel_err(bat, _oracle_grad(text, fb, fc)) <= 1e-4
+
+
+def test_batched_backward_ragged_last_group_and_slice_subrange(ctx):
+    """5 bitstrings x slices [1, 6) = 25 chains in groups of 8 (the last holds one chain): the
+    gradient equals the one-at-a-time backward over the same chains."""
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    _say("batched backward ragged")
+    c = generate(4, 5, 32, 2)
+    text = c.to_text()
+    qid = c.qubit_of()
+    cuts = [[qid[(1, 3)], qid[(2, 3)], 0, 2], [qid[(3, 1)], qid[(3, 2)], 1, 1]]
+    plan, _ = region_plan(c, 2, 2, cuts, [(3, 4), (2, 4)])
+    bits = random_bitstrings(5, 20, 9)
+    rng = np.random.default_rng(4)
+    cot = rng.normal(size=(5, 4)) + 1j * rng.normal(size=(5, 4))
+    seq = Plan(ctx, Circuit(ctx, text), plan, "fp32", backward=True).backward(bits, cot, 1, 6)
+    bat = Plan(ctx, Circuit(ctx, text), plan, "fp32", backward=True, batch=8).backward(bits, cot, 1, 6)
+    torch.cuda.synchronize()
+    assert rel_err(bat.cpu().numpy(), seq.cpu().numpy()) <= 1e-5
