@@ -185,7 +185,11 @@ qf_status qf_amplitudes(qf_plan* plan, int n_batch, const uint8_t* bits_dev, int
 /* Gradients of the amplitudes with respect to every gate entry (reverse sweep over the same
  * contraction tree with the same kernels, then through each world-line).  Needs a plan created
  * with QF_PLAN_BACKWARD.  For every slice in [s_begin, s_end) the forward pass is recomputed
- * and its environment tensors are propagated back.
+ * and its environment tensors are propagated back.  A batched backward plan (batch G > 1, not
+ * captured in a graph) runs G chains through every forward and reverse step at once; their
+ * leaf environments add atomically into shared world-line environments, so the order of the
+ * chains' terms in the gradient sums is not fixed (results differ from the one-chain-at-a-time
+ * plan by rounding only).
  *   cot_dev : device, n_batch x 2^n_open complex128 cotangents c_b of the amplitudes a_b
  *             (for L = sum |a_b|^2, c_b = 2 a_b).
  *   grad_dev: device, n_ops x 4 complex64 in the caller's gate order (2x2 row-major matrix, or
