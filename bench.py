@@ -37,10 +37,10 @@ def parse():
                     help="skip timing the GEMM kernel variants of the plans' shapes before the warmup")
     ap.add_argument("--calib-copy", action="store_true",
                     help="launch one plain 1 GiB device copy first (HBM counter calibration)")
-    ap.add_argument("--workload", default="7x7-d40", choices=["7x7-d40", "8x9-d24", "6x6-d24-grad", "11x11-d24", "vendor-gemm"],
+    ap.add_argument("--workload", default="7x7-d40", choices=["7x7-d40", "7x7-d32", "8x9-d24", "6x6-d24-grad", "11x11-d24", "vendor-gemm"],
                     help="7x7-d40: the benchmark line (default); 8x9-d24: 70 qubits, batched chains through a "
                          "captured graph, beside the searched plan; 6x6-d24-grad: forward and backward of 64 "
-                         "amplitudes; 11x11-d24: 121 qubits, a run of slices of the 64-slice region plan; vendor-gemm: the vendor real BF16 / FP32 GEMM on the same GPU (context for "
+                         "amplitudes; 7x7-d32: whole 16-slice path sums in FP32 beside split-BF16; 11x11-d24: 121 qubits, a run of slices of the 64-slice region plan; vendor-gemm: the vendor real BF16 / FP32 GEMM on the same GPU (context for "
                          "the roofline: what the matrix cores sustain under the power limit)")
     return ap.parse_args()
 
@@ -178,6 +178,45 @@ def bench_6x6_grad(args):
                       "forward_batched_rel_diff": diff, "backward_batched_s": bwd_b,
                       "backward_batched_rel_diff": gdiff,
                       "gates": int(g.shape[0]), "data": "synthetic, seeded"}), flush=True)
+    return 0
+
+
+def bench_7x7_d32(args):
+    """7x7 (1+32+1), bond 16: the region plan with one cut (16 slices, peak 2^28), 6 open qubits
+    (64 amplitudes per prefix), whole path sums of seeded prefixes in plain FP32; beside it the
+    same in split-BF16, and FP32 with the renormalisation off (its cost)."""
+    import torch
+    from paper_1905_00444_amd import Context, Circuit, Plan, autotune
+    from workloads.bitstrings import random_bitstrings
+    from workloads.circuits import generate
+    from workloads.plans import plan_7x7
+    circ = generate(7, 7, 32, 0)
+    plan, _ = plan_7x7(circ, 32)
+    P = max(1, args.steps)
+    bits = random_bitstrings(P, 49, 1)
+    ctx = Context(0)
+    cobj = Circuit(ctx, circ.to_text())
+    res = {}
+    for name, prec, renorm in (("fp32", "fp32", True), ("bf16x3", "bf16x3", True), ("fp32_no_renorm", "fp32", False)):
+        p = Plan(ctx, cobj, plan, prec, renorm=renorm)
+        if not args.no_autotune:
+            autotune(p)
+        p.amplitudes(bits[:1], 0, 1)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = p.amplitudes(bits)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fl = P * p.flops(0, p.info()["n_slices"])
+        res[name] = {"seconds": dt, "amplitudes_per_s": 64 * P / dt, "complex_tflops": fl / dt / 1e12}
+        res[name + "_out"] = out
+    rel = float((torch.linalg.vector_norm(res["bf16x3_out"] - res["fp32_out"])
+                 / torch.linalg.vector_norm(res["fp32_out"])).item())
+    same = bool(torch.equal(res["fp32_out"], res["fp32_no_renorm_out"]))
+    print(json.dumps({"metric": "7x7 (1+32+1) amplitudes, 16-slice path sums", "n_gpus": 1, "prefixes": P,
+                      "amplitudes": 64 * P, "fp32": res["fp32"], "bf16x3": res["bf16x3"],
+                      "fp32_no_renorm": res["fp32_no_renorm"], "rel_err_bf16x3_vs_fp32": rel,
+                      "renorm_bitwise_equal": same, "data": "synthetic, seeded"}), flush=True)
     return 0
 
 
@@ -320,6 +359,8 @@ def main():
         return bench_8x9(args)
     if args.workload == "11x11-d24":
         return bench_11x11(args)
+    if args.workload == "7x7-d32":
+        return bench_7x7_d32(args)
     if args.workload == "6x6-d24-grad":
         return bench_6x6_grad(args)
     if args.workload == "vendor-gemm":
