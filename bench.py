@@ -212,11 +212,32 @@ def bench_7x7_d32(args):
         res[name + "_out"] = out
     rel = float((torch.linalg.vector_norm(res["bf16x3_out"] - res["fp32_out"])
                  / torch.linalg.vector_norm(res["fp32_out"])).item())
+    # frugal rejection sampling (paper Sec. III-B) fed by split-BF16 path sums of fresh prefixes
+    from paper_1905_00444_amd import sampling
+    passes = 8 * P
+    pre = random_bitstrings(passes, 49, 2)
+    ps = Plan(ctx, cobj, plan, "bf16x3")
+    t0 = time.perf_counter()
+    amps = ps.amplitudes(pre).cpu().numpy()
+    smp, acc = sampling.frugal_rejection_sample(amps, pre, plan["open"], 49, M=10.0,
+                                                rng=np.random.default_rng(5))
+    t_s = time.perf_counter() - t0
+    probs = []
+    for i in np.flatnonzero(acc):
+        j = 0
+        for t, q in enumerate(plan["open"]):
+            j |= int(smp[i, q]) << (len(plan["open"]) - 1 - t)
+        probs.append(abs(amps[i, j]) ** 2)
+    sample_rec = {"passes": passes, "accepted": int(acc.sum()), "seconds": t_s,
+                  "samples_per_s": float(acc.sum()) / t_s,
+                  "xeb_linear": sampling.xeb_linear(np.array(probs), 49) if probs else None,
+                  "xeb_linear_all_completions": sampling.xeb_linear(np.abs(amps.reshape(-1)) ** 2, 49)}
     same = bool(torch.equal(res["fp32_out"], res["fp32_no_renorm_out"]))
     print(json.dumps({"metric": "7x7 (1+32+1) amplitudes, 16-slice path sums", "n_gpus": 1, "prefixes": P,
                       "amplitudes": 64 * P, "fp32": res["fp32"], "bf16x3": res["bf16x3"],
                       "fp32_no_renorm": res["fp32_no_renorm"], "rel_err_bf16x3_vs_fp32": rel,
-                      "renorm_bitwise_equal": same, "data": "synthetic, seeded"}), flush=True)
+                      "renorm_bitwise_equal": same, "sampling": sample_rec, "data": "synthetic, seeded"}),
+          flush=True)
     return 0
 
 
