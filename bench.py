@@ -46,8 +46,8 @@ def parse():
 
 
 def bench_8x9(args):
-    """70 qubits (8x9 minus two corners, 1+24+1, bond 8): 16 bitstrings x 64 of the 256 slices of
-    the two-halves plan as 1024 chains, 16 per launch, replayed from one captured hipGraph; and the
+    """70 qubits (8x9 minus two corners, 1+24+1, bond 8): 16 bitstrings x all 256 slices of the
+    two-halves plan as 4096 chains, 16 per launch, replayed from one captured hipGraph; and the
     whole amplitudes of the same 16 bitstrings with the plan the search finds (no cut at 2^27)."""
     import torch
     from paper_1905_00444_amd import Context, Circuit, Plan, planner
@@ -62,7 +62,7 @@ def bench_8x9(args):
     cobj = Circuit(ctx, text)
     rec = {"metric": "70-qubit (8x9 - 2, 1+24+1) amplitudes", "n_gpus": 1, "data": "synthetic, seeded",
            "dtype": "bf16x3 (FP32 accumulate)"}
-    G, S = 16, 64
+    G, S = 16, 256
     p = Plan(ctx, cobj, hand, "bf16x3", batch=G, graph=True)
     with torch.cuda.stream(ctx.stream):
         bits_t = torch.from_numpy(bits).to(ctx.device)  # one device copy: the captured graph keys on it
@@ -80,6 +80,7 @@ def bench_8x9(args):
     rec["batched_graph"] = {"chains": chains, "chains_per_launch": G, "slices": S, "seconds": dt,
                             "chains_per_s": chains / dt, "complex_tflops": fl / dt / 1e12,
                             "plan": "two halves, cuts (0,4)-(0,5) 3 bits, (1,4)-(1,5) 3 bits, (2,4)-(2,5) 2 bits"}
+    hand_amps = out.cpu().numpy()
     del p
     best = planner.search(text, 27)
     q = Plan(ctx, cobj, best.plan, "bf16x3")
@@ -95,7 +96,9 @@ def bench_8x9(args):
     a, b = full.cpu().numpy(), f32.cpu().numpy()
     rec["searched_plan"] = {"amplitudes": 16, "seconds": dt, "amplitudes_per_s": 16 / dt,
                             "complex_tflops": 16 * q.info()["flops_per_slice"] / dt / 1e12,
-                            "plan": repr(best), "rel_err_bf16x3_vs_fp32": float(norm(a - b) / norm(b))}
+                            "plan": repr(best), "rel_err_bf16x3_vs_fp32": float(norm(a - b) / norm(b)),
+                            # all 256 slices of the hand plan sum to the same amplitudes (plan invariance)
+                            "rel_diff_vs_hand_plan_path_sum": float(norm(hand_amps - a) / norm(a))}
     print(json.dumps(rec), flush=True)
     return 0
 
