@@ -68,6 +68,7 @@ def bench_8x9(args):
         bits_t = torch.from_numpy(bits).to(ctx.device)  # one device copy: the captured graph keys on it
     out = p.amplitudes(bits_t, 0, S)  # captures the graph, warms up
     ctx.synchronize()
+    print("bench: 8x9 graph captured, warm-up pass done", file=sys.stderr, flush=True)
     with torch.cuda.stream(ctx.stream):
         out.zero_()
     ctx.synchronize()
@@ -81,6 +82,7 @@ def bench_8x9(args):
                             "chains_per_s": chains / dt, "complex_tflops": fl / dt / 1e12,
                             "plan": "two halves, cuts (0,4)-(0,5) 3 bits, (1,4)-(1,5) 3 bits, (2,4)-(2,5) 2 bits"}
     hand_amps = out.cpu().numpy()
+    print(f"bench: 8x9 timed pass {dt:.1f} s", file=sys.stderr, flush=True)
     del p
     best = planner.search(text, 27)
     q = Plan(ctx, cobj, best.plan, "bf16x3")
