@@ -76,8 +76,11 @@ enum {
                            subtrees across slices) */
   QF_PLAN_BACKWARD = 2, /* keep every forward tensor and reserve environment buffers so that
                            qf_backward can run (implies QF_PLAN_NO_HOIST; larger workspace) */
-  QF_PLAN_GRAPH = 4,    /* batched plans: capture one group's launches in a hipGraph and replay it
-                           for every group (needs a non-null stream) */
+  QF_PLAN_GRAPH = 4,    /* batched plans (needs a non-null stream): a qf_amplitudes call is captured
+                           once, whole (every group of G chains), in a hipGraph, and each later
+                           call with the same buffers, batch and slice range is one
+                           hipGraphLaunch.  Replaces the paper's pipelined execution of
+                           concurrent tensor operations (Sec. III-E). */
   QF_PLAN_NO_RENORM = 8 /* store every intermediate at its true scale.  By default (Sec. III-E:
                            normalise the inputs, renormalise at the end) each stored tensor keeps
                            a power-of-two exponent on the device: a contraction divides its
@@ -144,7 +147,11 @@ typedef struct qf_plan qf_plan;
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t, may be
  * NULL for the null stream).  workspace/ws_bytes: caller-owned device memory (256-byte
- * aligned) the library uses for every tensor; it may be NULL/0 now and set later. */
+ * aligned) the library uses for every tensor; it may be NULL/0 now and set later.  The paper's
+ * GPU back-end keeps every tensor in buffers allocated once at start-up, with its own allocator
+ * inside them, and runs its operations asynchronously on streams (Sec. III-E); here the one
+ * buffer is the caller's workspace with offsets fixed at plan time, and the stream is the
+ * caller's.  Errors: QF_ERR_ARG (null out, workspace not 256-byte aligned). */
 qf_status qf_ctx_create(int device, void* hip_stream, void* workspace, size_t ws_bytes, qf_ctx** out);
 qf_status qf_ctx_set_workspace(qf_ctx* ctx, void* workspace, size_t ws_bytes);
 qf_status qf_ctx_set_stream(qf_ctx* ctx, void* hip_stream);
@@ -155,20 +162,37 @@ void qf_ctx_destroy(qf_ctx* ctx);
 const char* qf_last_error(const qf_ctx* ctx);
 
 /* Circuit on a rows x cols grid; present[r*cols+c] != 0 marks a live site (NULL = all).
- * Host arrays are copied.  Errors: QF_ERR_ARG for out-of-range or non-adjacent qubits. */
+ * The circuits of the paper are planar grids whose only two-qubit gates are CZs between adjacent
+ * qubits (Sec. III); each gate is a tensor of the circuit's network (Sec. II, tensor-network
+ * simulators), and a diagonal two-qubit gate becomes one bond bit between its qubits' world-lines
+ * (Sec. III, Fig. 3 caption).  ops: n_ops gates, any order (sorted by cycle, ties keep their
+ * order).  Host arrays are copied; the caller keeps ownership.  Errors: QF_ERR_ARG for null or
+ * out-of-range arguments and non-adjacent qubits, QF_ERR_UNSUPPORTED for fewer than 2 qubits. */
 qf_status qf_circuit_create(qf_ctx* ctx, int rows, int cols, const uint8_t* present, int n_ops,
                             const qf_op* ops, qf_circuit** out);
 /* Replace all gate values (n_ops * 8 floats, same layout as qf_op.values). */
 qf_status qf_circuit_set_values(qf_circuit* circ, const float* values);
 void qf_circuit_destroy(qf_circuit* circ);
 
-/* Validate a plan against a circuit and lay out its workspace (host only). */
+/* Validate a plan against a circuit and lay out its workspace (host only).  The plan is the
+ * paper's contraction order (Sec. III-D), its cuts (Sec. III-A: each slice is an independent
+ * network, the amplitude is the sum over slices) and its open output qubits (Sec. III-B: the root
+ * keeps their output legs, 2^n_open amplitudes per pass); every step becomes a permute of each
+ * operand and a complex GEMM (the transpose-GEMM-transpose scheme of Sec. III-E).  Errors:
+ * QF_ERR_ARG (null arguments, unknown precision, batch not a power of two), QF_ERR_PLAN (a node used
+ * twice or before it exists, a root that keeps bonds, a cut off a bond or past its bits, bad open
+ * qubits), QF_ERR_UNSUPPORTED (sizes beyond the library's limits).  The message says which. */
 qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* desc, qf_plan** out);
 qf_status qf_plan_info_get(const qf_plan* plan, qf_plan_info* out);
 /* Algorithmic flops (sum of 8 sqrt(v0 v1 v2) over executed steps) that qf_amplitudes performs
  * for ONE bitstring over slices [s_begin, s_end), counting the reuse of steps whose inputs do
  * not change from one slice to the next (host only). */
 qf_status qf_plan_flops(const qf_plan* plan, int64_t s_begin, int64_t s_end, double* flops);
+/* Graph execution of a batched plan created with QF_PLAN_GRAPH (host only): *launches = the
+ * hipGraphLaunch calls made for this plan so far (one per qf_amplitudes call), *nodes = the nodes
+ * of the graph currently captured (0 before the first call).  Errors: QF_ERR_ARG (null pointer),
+ * QF_ERR_HIP. */
+qf_status qf_plan_graph_info(const qf_plan* plan, int64_t* launches, int64_t* nodes);
 /* Description of step i (0 <= i < n_steps) of a laid-out plan (host only). */
 qf_status qf_plan_step_info(const qf_plan* plan, int i, qf_step_info* out);
 void qf_plan_destroy(qf_plan* plan);
@@ -252,8 +276,9 @@ qf_status qf_time_cgemm(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_
 qf_status qf_time_permute(qf_ctx* ctx, const void* src, void* dst, int nbits, const int32_t* perm,
                           int reps, float* ms);
 
-/* Autotuning of the GEMM kernels that a plan launches (the paper's GPU back-end picks its
- * kernels by shape class, Sec. III-F; here the choice is measured).  For every distinct GEMM
+/* Autotuning of the GEMM kernels that a plan launches.  Not in the paper, whose contractions
+ * call the vendor library's default complex GEMM (Sec. III-E); here the kernel for each shape is
+ * chosen by measurement.  For every distinct GEMM
  * shape among the plan's steps (precision, M, N, K, chains per launch) the kernel variants that
  * fit the shape are timed with HIP events on pseudo-random operands placed in the plan's own
  * workspace buffers, and the fastest is installed in the context: every later launch of that

@@ -12,7 +12,7 @@ Modules
     parse    own parser of the circuit text format and plan dictionaries
     sv       direct state-vector evolution (paper Sec. II, first simulator
              class): the plain definition a(x) = <x| U |0...0>; and the state
-             of one path of the sliced sum (Sec. III-A, III-D)
+             of one path of the sliced sum (Sec. III-A, III-C)
     tn       tensor-network route (paper Sec. II, tensor-network class, and
              Sec. III): time-first world-line tensors, sliced pairwise
              contraction in a given plan order, complex128 throughout

@@ -12,6 +12,8 @@ gate t),
     diagonal D on q0,q1: grad[k]   = sum_{idx in class k} chi_t[idx] conj(psi_t[idx])
 Pinned in the tests by central finite differences, which are exact here
 because L_c(G) = sum_b Re(conj(c_b) a_b(G)) is linear in every entry.
+Gradients are not part of the paper; the amplitudes they differentiate are those
+of the circuit's tensor network (paper Sec. II).
 """
 from __future__ import annotations
 
@@ -79,3 +81,28 @@ def fd_gradient(circ, bits: np.ndarray, cot: np.ndarray, op_index: int, h: float
             parts.append((lp - lm) / (2 * h))
         g[idx] = parts[0] + 1j * parts[1]
     return g
+
+
+def fd_norm_loss_tn(circ, bits: np.ndarray, plan: dict, op_index: int, entry: int, h: float = 1e-2) -> complex:
+    """Gradient of L = sum over bitstrings b and completions j of |a_bj|^2 with respect to one
+    entry of one gate (entry: flat index into the 2x2 matrix, or into the 4 diagonal entries),
+    as central finite differences of L evaluated by the tensor-network route (tn.amplitudes with
+    `plan`), for circuits beyond the state vector's reach.  Returns dL/dRe + i dL/dIm.
+    Every amplitude is linear in each gate entry, so L is a quadratic polynomial of it and the
+    central difference carries no truncation error for any h (only rounding)."""
+    from . import tn
+    if isinstance(circ, str):
+        circ = read_circuit(circ)
+    base = [np.array(v, dtype=np.complex128) for v in circ.values]
+    shape = base[op_index].shape
+    idx = np.unravel_index(entry, shape)
+    parts = []
+    for step in (h, 1j * h):
+        losses = []
+        for sign in (1.0, -1.0):
+            vals = [v.copy() for v in base]
+            vals[op_index][idx] += sign * step
+            a = tn.amplitudes(circ.with_values(vals), bits, plan)
+            losses.append(float(np.sum(np.abs(a) ** 2)))
+        parts.append((losses[0] - losses[1]) / (2 * h))
+    return complex(parts[0], parts[1])

@@ -10,22 +10,17 @@ import numpy as np
 
 
 def rel_err(a: np.ndarray, ref: np.ndarray) -> float:
+    """||a - ref||_2 / ||ref||_2 over the whole batch (||a - ref|| if ref is all zero)."""
     a = np.asarray(a, dtype=np.complex128).reshape(-1)
     ref = np.asarray(ref, dtype=np.complex128).reshape(-1)
     den = np.linalg.norm(ref)
     return float(np.linalg.norm(a - ref) / den) if den > 0 else float(np.linalg.norm(a - ref))
 
 
-def max_err_over_rms(a: np.ndarray, ref: np.ndarray) -> float:
-    a = np.asarray(a, dtype=np.complex128).reshape(-1)
-    ref = np.asarray(ref, dtype=np.complex128).reshape(-1)
-    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
-    return float(np.max(np.abs(a - ref)) / rms)
-
-
 def porter_thomas(amps: np.ndarray, n_qubits: int):
     """For p = |a|^2 of uniformly drawn bitstrings, N p ~ Exp(1) for deep random
-    circuits: returns (mean of N p, mean of (N p)^2, KS distance to 1 - e^-x)."""
+    circuits (N = 2^n_qubits): returns (mean of N p, mean of (N p)^2, Kolmogorov-Smirnov
+    distance between the empirical distribution of N p and 1 - e^-x)."""
     p = np.abs(np.asarray(amps).reshape(-1)) ** 2 * (2.0 ** n_qubits)
     xs = np.sort(p)
     m = len(xs)

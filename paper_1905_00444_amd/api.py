@@ -37,11 +37,18 @@ class Context:
         self.ws = None
 
     def ensure_workspace(self, nbytes: int) -> None:
+        """Grow the workspace to at least nbytes.  The old buffer may still be in use by work
+        queued on the context's stream: it is released only after that work (the stream is
+        synchronised first), and the new one is allocated on the context's stream so that the
+        caching allocator orders its reuse after the library's kernels."""
         torch = _torch()
         nbytes = max(int(nbytes), 4096)
         if self.ws is None or self.ws.numel() < nbytes:
-            self.ws = None
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if self.ws is not None:
+                self.stream.synchronize()
+                self.ws = None
+            with torch.cuda.stream(self.stream):
+                self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             check(self.lib.qf_ctx_set_workspace(self.h, C.c_void_p(self.ws.data_ptr()), self.ws.numel()), self.h)
 
     def synchronize(self) -> None:
@@ -164,11 +171,15 @@ class Plan:
         check(ctx.lib.qf_plan_create(ctx.h, circuit.h, C.byref(d), C.byref(h)), ctx.h)
         self.h = h
         self.n_open = len(opn)
+        self._info = None
 
     def info(self) -> dict:
-        inf = _lib.qf_plan_info()
-        check(self.ctx.lib.qf_plan_info_get(self.h, C.byref(inf)), self.ctx.h)
-        return {k: getattr(inf, k) for k, _ in _lib.qf_plan_info._fields_}
+        """Sizes, flops and workspace of the plan (qf_plan_info_get; fixed at creation, read once)."""
+        if self._info is None:
+            inf = _lib.qf_plan_info()
+            check(self.ctx.lib.qf_plan_info_get(self.h, C.byref(inf)), self.ctx.h)
+            self._info = {k: getattr(inf, k) for k, _ in _lib.qf_plan_info._fields_}
+        return dict(self._info)
 
     def steps(self) -> list:
         """Per-step layout the plan chose (TTGT roles, GEMM sizes, which operands are copied)."""
@@ -178,6 +189,12 @@ class Plan:
             check(self.ctx.lib.qf_plan_step_info(self.h, i, C.byref(si)), self.ctx.h)
             out.append({k: getattr(si, k) for k, _ in _lib.qf_step_info._fields_})
         return out
+
+    def graph_info(self) -> tuple:
+        """(hipGraphLaunch calls so far, nodes of the captured graph) of a graph-captured plan."""
+        launches, nodes = C.c_int64(), C.c_int64()
+        check(self.ctx.lib.qf_plan_graph_info(self.h, C.byref(launches), C.byref(nodes)), self.ctx.h)
+        return launches.value, nodes.value
 
     def flops(self, s_begin: int, s_end: int) -> float:
         """Executed algorithmic flops for one bitstring over slices [s_begin, s_end)."""

@@ -772,16 +772,6 @@ static hipError_t launch_tiled(hipStream_t st, int64_t M, int64_t N, int64_t K, 
   return hipGetLastError();
 }
 
-static int g_gemm_variant = -1;  // -1: not read yet; 0: v1 tiles only; 1: large-tile kernel where it fits
-
-static bool use_v2() {
-  if (g_gemm_variant < 0) {
-    const char* e = getenv("QFMI_GEMM_V1");
-    g_gemm_variant = (e && e[0] == '1') ? 0 : 1;
-  }
-  return g_gemm_variant == 1;
-}
-
 static bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 bool cgemm_variant_fits(int precision, int64_t M, int64_t N, int64_t K, int variant) {
@@ -800,7 +790,7 @@ bool cgemm_variant_fits(int precision, int64_t M, int64_t N, int64_t K, int vari
 }
 
 int cgemm_default_variant(int precision, int64_t M, int64_t N, int64_t K) {
-  if (use_v2() && cgemm_variant_fits(precision, M, N, K, GEMM_LARGE)) return GEMM_LARGE;
+  if (cgemm_variant_fits(precision, M, N, K, GEMM_LARGE)) return GEMM_LARGE;
   // HBM-bound tall-skinny products below the tiles' N and K (as fast as the 64 x 32 tiles where
   // those fit: 5.1 TB/s on 2^25 x 32 x 32 split-BF16)
   if (M >= 4096 && (N < 32 || K < kBK) && cgemm_variant_fits(precision, M, N, K, GEMM_TALL)) return GEMM_TALL;

@@ -2,16 +2,14 @@
 // "G" of transpose-GEMM-transpose; see cgemm.hip for the real embedding and the split).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
-#include <stdlib.h>
-#include <string>
 #include "cgemm_common.h"
 
 namespace qf {
 
 // Large shapes, split-BF16 on operands already split in HBM (hi and lo planes of bfloat16
-// complex numbers, [rows][K] each, written by the permute that precedes the GEMM).  Same
-// tiling as the kernel above (256 x 128 complex block, 8 waves of 4 x 8 MFMA tiles, K-tiles of
-// 16 complex) but the operands travel HBM -> LDS directly (global_load_lds_dwordx4: each lane
+// complex numbers, [rows][K] each, written by the permute that precedes the GEMM).  A 256 x 128
+// complex block per workgroup, 8 waves, K-tiles of 16 complex; the operands travel HBM -> LDS
+// directly (global_load_lds_dwordx4: each lane
 // moves 16 bytes, one instruction fills 1 KiB = 16 rows x 64 bytes of one plane), through a
 // ring of 3 LDS stages: while tile kt is multiplied, tiles kt+1 and kt+2 are in flight.  Each
 // wave waits only for its own loads of tile kt (vmcnt), then one barrier makes every wave's
@@ -52,118 +50,12 @@ __device__ __forceinline__ void v3_issue(char* stage, const uint32_t* __restrict
   }
 }
 
-// Wave tile WI x WJ MFMA tiles (16 WI rows x 8 WJ complex columns); the 8 waves tile the 256 x 128
-// block as (16 / WI) x (16 / WJ).  The B operand (the expanded one) costs 2 VALU operations per
-// dword per wave, so a narrower wave tile in N halves that work at the same MFMA count.
-template <int WI, int WJ>
-__global__ void __launch_bounds__(kV3Threads)
-cgemm_v3_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
-                  const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl, float2* __restrict__ C,
-                  int64_t lda, int64_t ldb, int64_t sa, int64_t sb, int64_t sc, Renorm rn) {
-  __shared__ __attribute__((aligned(1024))) char lds[kV3Stages * kV3Stage];
-
-  const int64_t tiles_m = M / kV3BM, tiles_n = N / kV3BN;
-  const int64_t ntiles = tiles_m * tiles_n;
-  int64_t bid = blockIdx.x;
-  if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
-  const int64_t group = 8;
-  const int64_t per_group = group * tiles_n;
-  const int64_t gidx = bid / per_group;
-  const int64_t first_m = gidx * group;
-  const int64_t gsize = (tiles_m - first_m) < group ? (tiles_m - first_m) : group;
-  const int64_t tm = first_m + (bid % per_group) % gsize;
-  const int64_t tn = (bid % per_group) / gsize;
-
-  const int64_t batch = blockIdx.z;
-  Ah += batch * sa + tm * kV3BM * lda;
-  Al += batch * sa + tm * kV3BM * lda;
-  Bh += batch * sb + tn * kV3BN * ldb;
-  Bl += batch * sb + tn * kV3BN * ldb;
-  C += batch * sc;
-
-  static_assert(WI * WJ == 32 && 16 * WI <= kV3BM && 8 * WJ <= kV3BN, "8 waves cover the block tile");
-  constexpr int NWN = kV3BN / (8 * WJ);  // waves along N
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave / NWN) * (16 * WI);
-  const int wc = (wave % NWN) * (8 * WJ);
-  const int l16 = lane & 15, lg = lane >> 4, q = l16 & 1;
-  const BExpand bx(q);
-  // swizzled 16-byte chunk of this lane's operand reads
-  const int a_chunk = (lg ^ ((l16 >> 1) & 3)) * 16;
-
-  f4 acc[WI][WJ];
-#pragma unroll
-  for (int i = 0; i < WI; ++i)
-#pragma unroll
-    for (int j = 0; j < WJ; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
-
-  const int64_t nk = K / kV3BK;
-  v3_issue(lds, Ah, Al, Bh, Bl, lda, ldb, 0, wave, lane);
-  if (nk > 1) v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, lda, ldb, kV3BK, wave, lane);
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
-    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    if (kt + 2 < nk) v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, lda, ldb, (kt + 2) * kV3BK, wave, lane);
-    const char* st = lds + (kt % kV3Stages) * kV3Stage;
-    u4 ah[WI], al[WI];
-#pragma unroll
-    for (int i = 0; i < WI; ++i) {
-      const char* p = st + (wr + 16 * i + l16) * 64 + a_chunk;
-      ah[i] = *reinterpret_cast<const u4*>(p);
-      al[i] = *reinterpret_cast<const u4*>(p + kV3PlaneA);
-    }
-#pragma unroll
-    for (int j = 0; j < WJ; ++j) {
-      const int row = wc + 8 * j + (l16 >> 1);
-      const char* p = st + 2 * kV3PlaneA + row * 64 + (lg ^ ((row >> 1) & 3)) * 16;
-      u4 bh = *reinterpret_cast<const u4*>(p);
-      u4 bl = *reinterpret_cast<const u4*>(p + kV3PlaneB);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) { bh[e] = bx(bh[e]); bl[e] = bx(bl[e]); }
-      const bf8 vbh = __builtin_bit_cast(bf8, bh), vbl = __builtin_bit_cast(bf8, bl);
-#pragma unroll
-      for (int i = 0; i < WI; ++i)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, al[i]), vbh, acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < WI; ++i)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), vbl, acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < WI; ++i)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), vbh, acc[i][j], 0, 0, 0);
-    }
-  }
-
-  // renormalisation is read only now, so that nothing else is in flight during the load ring
-  float scale_a, scale_b, unscale;
-  renorm_begin<P_BF16X3>(rn, nullptr, nullptr, scale_a, scale_b, unscale);
-  float mx = 0.f;
-#pragma unroll
-  for (int i = 0; i < WI; ++i)
-#pragma unroll
-    for (int j = 0; j < WJ; ++j) {
-      const f4 v = acc[i][j] * unscale;
-      const float s0 = q ? v[0] : v[2], s1 = q ? v[1] : v[3];
-      const float r0 = __shfl_xor(s0, 1), r1 = __shfl_xor(s1, 1);
-      const int64_t row = tm * kV3BM + wr + 16 * i + 4 * lg + (q ? 2 : 0);
-      const int64_t col = tn * kV3BN + wc + 8 * j + (l16 >> 1);
-      float2 o0, o1;
-      if (q) { o0 = make_float2(r0, v[2]); o1 = make_float2(r1, v[3]); }
-      else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
-      C[row * N + col] = o0;
-      C[(row + 1) * N + col] = o1;
-      mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
-    }
-  if (rn.c) record_amax(rn.c, mx);
-}
-
-// Same block tile, load ring and LDS layout as above, with the B fragments double-buffered in
-// registers: each wave holds the expanded B fragments of the current K-tile, streams A in row
-// groups, and halfway through the tile waits for its own loads of the next tile, meets the other
-// waves at the barrier, issues the tile after next and reads (and expands) the next tile's B
-// fragments while its remaining MFMAs run.  A K-tile thus starts with its operands already in
-// registers instead of a full LDS-read stall, and one barrier per K-tile remains.
-constexpr int kV4WI = 8, kV4WJ = 4;  // wave tile: 128 rows x 32 complex columns
+// Each wave owns a 128-row x 32-complex-column tile of the block (8 x 4 MFMA tiles of 16 x 16
+// real outputs; the 8 waves tile the block 2 x 4).  Per K-tile a wave reads its B fragments once
+// after the barrier (expanding each packed complex into the real column the lane computes, see
+// BExpand), then streams A row group by row group: the compiler overlaps the A reads of one
+// group with the MFMAs of the previous.
+constexpr int kV4WI = 8, kV4WJ = 4;
 
 __device__ __forceinline__ void v4_load_b(const char* st, int wc, int l16, int lg, const BExpand& bx,
                                           u4 (&bh)[kV4WJ], u4 (&bl)[kV4WJ]) {
@@ -183,12 +75,12 @@ __device__ __forceinline__ void v4_load_b(const char* st, int wc, int l16, int l
     }
 }
 
-// MFMAs of row groups [I0, I1) of one K-tile against the B fragments in registers.
-template <int I0, int I1>
+// MFMAs of every row group of one K-tile against the B fragments in registers: lo x hi, hi x lo,
+// then hi x hi, so the largest product is added last.
 __device__ __forceinline__ void v4_rows(const char* st, int wr, int l16, int a_chunk, const u4 (&bh)[kV4WJ],
                                         const u4 (&bl)[kV4WJ], f4 (&acc)[kV4WI][kV4WJ]) {
 #pragma unroll
-  for (int i = I0; i < I1; ++i) {
+  for (int i = 0; i < kV4WI; ++i) {
     const char* p = st + (wr + 16 * i + l16) * 64 + a_chunk;
     const bf8 ah = __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(p));
     const bf8 al = __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(p + kV3PlaneA));
@@ -204,22 +96,22 @@ __device__ __forceinline__ void v4_rows(const char* st, int wr, int l16, int a_c
   }
 }
 
-// DB = false (the default schedule): no double-buffering; each K-tile reads its B fragments after
-// the barrier and then streams A row group by row group, the compiler overlapping the A reads of
-// one group with the MFMAs of the previous.  DB = true keeps two B fragment sets in registers
-// (256 VGPRs, which leaves the compiler no room to overlap the A reads; slower).
-template <bool DB>
+// Row tiles per raster group: after the XCD-aware reordering, the 32 workgroups that run together
+// on one XCD share 4 A panels and 8 B panels in that XCD's L2.
+constexpr int kV4GroupRows = 4;
+
 __global__ void __launch_bounds__(kV3Threads)
 cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
                   const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl, float2* __restrict__ C,
-                  int64_t lda, int64_t ldb, int64_t sa, int64_t sb, int64_t sc, Renorm rn, int group_rows) {
+                  int64_t lda, int64_t ldb, int64_t sa, int64_t sb, int64_t sc, Renorm rn) {
   __shared__ __attribute__((aligned(1024))) char lds[kV3Stages * kV3Stage];
 
+  // workgroups are dealt round-robin to the 8 XCDs: give consecutive tiles to one XCD
   const int64_t tiles_m = M / kV3BM, tiles_n = N / kV3BN;
   const int64_t ntiles = tiles_m * tiles_n;
   int64_t bid = blockIdx.x;
   if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
-  const int64_t group = group_rows;  // row tiles per raster group
+  const int64_t group = kV4GroupRows;
   const int64_t per_group = group * tiles_n;
   const int64_t gidx = bid / per_group;
   const int64_t first_m = gidx * group;
@@ -250,52 +142,21 @@ cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
     for (int j = 0; j < WJ; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
 
   const int64_t nk = K / kV3BK;
-  if constexpr (!DB) {
-    v3_issue(lds, Ah, Al, Bh, Bl, lda, ldb, 0, wave, lane);
-    if (nk > 1) v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, lda, ldb, kV3BK, wave, lane);
-    for (int64_t kt = 0; kt < nk; ++kt) {
-      if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
-      else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __builtin_amdgcn_s_barrier();
-      if (kt + 2 < nk)
-        v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, lda, ldb, (kt + 2) * kV3BK, wave, lane);
-      const char* st = lds + (kt % kV3Stages) * kV3Stage;
-      u4 bh[WJ], bl[WJ];
-      v4_load_b(st, wc, l16, lg, bx, bh, bl);
-      v4_rows<0, WI>(st, wr, l16, a_chunk, bh, bl, acc);
-    }
-  }
-  if constexpr (DB) {
   v3_issue(lds, Ah, Al, Bh, Bl, lda, ldb, 0, wave, lane);
-  if (nk > 1) {
-    v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, lda, ldb, kV3BK, wave, lane);
-    asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
-  } else {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  }
-  __builtin_amdgcn_s_barrier();
-  u4 fbh[WJ], fbl[WJ], gbh[WJ], gbl[WJ];
-  v4_load_b(lds, wc, l16, lg, bx, fbh, fbl);
-
-  // one K-tile: first half of the rows, hand-over to the next tile, second half
-  auto tile = [&](int64_t kt, const u4 (&bh)[WJ], const u4 (&bl)[WJ], u4 (&nbh)[WJ], u4 (&nbl)[WJ]) {
+  if (nk > 1) v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, lda, ldb, kV3BK, wave, lane);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    if (kt + 2 < nk)
+      v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, lda, ldb, (kt + 2) * kV3BK, wave, lane);
     const char* st = lds + (kt % kV3Stages) * kV3Stage;
-    v4_rows<0, WI / 2>(st, wr, l16, a_chunk, bh, bl, acc);
-    if (kt + 1 < nk) {
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's loads of tile kt+1
-      __builtin_amdgcn_s_barrier();                      // everyone's loads of kt+1; everyone past tile kt-1
-      if (kt + 2 < nk)
-        v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, lda, ldb, (kt + 2) * kV3BK, wave, lane);
-      v4_load_b(lds + ((kt + 1) % kV3Stages) * kV3Stage, wc, l16, lg, bx, nbh, nbl);
-    }
-    v4_rows<WI / 2, WI>(st, wr, l16, a_chunk, bh, bl, acc);
-  };
-  for (int64_t kt = 0; kt < nk; kt += 2) {
-    tile(kt, fbh, fbl, gbh, gbl);
-    if (kt + 1 < nk) tile(kt + 1, gbh, gbl, fbh, fbl);
-  }
+    u4 bh[WJ], bl[WJ];
+    v4_load_b(st, wc, l16, lg, bx, bh, bl);
+    v4_rows(st, wr, l16, a_chunk, bh, bl, acc);
   }
 
+  // renormalisation is read only now, so that nothing else is in flight during the load ring
   float scale_a, scale_b, unscale;
   renorm_begin<P_BF16X3>(rn, nullptr, nullptr, scale_a, scale_b, unscale);
   float mx = 0.f;
@@ -342,37 +203,9 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
   const uint32_t* al = a + M * lda;
   const uint32_t* bl = b + N * ldb;
   const int64_t tiles = (M / kV3BM) * (N / kV3BN);
-  // QFMI_V3_WAVES=64x64 / 128x32 / db select the other schedules (comparison runs); the default
-  // streams A row groups against B fragments read at the start of each K-tile (fastest measured:
-  // 430 vs 423 (128x32), 408 (64x64) and 398 (db) TFLOP/s on 8192^3 and 2^15-cubed; raising the
-  // wave priority around the MFMAs measured 2% slower)
-  static const int variant = [] {
-    const char* e = getenv("QFMI_V3_WAVES");
-    if (e && std::string(e) == "64x64") return 1;
-    if (e && std::string(e) == "128x32") return 2;
-    if (e && std::string(e) == "db") return 0;
-    return 3;
-  }();
   const dim3 grid((unsigned)tiles, 1, (unsigned)batch);
-  // row tiles per raster group: the 32 workgroups that run together on one XCD then share 4 A
-  // panels and 8 B panels (QFMI_V3_GROUP overrides, comparison runs)
-  static const int group_rows = [] {
-    const char* e = getenv("QFMI_V3_GROUP");
-    const int g = e ? atoi(e) : 4;
-    return (g >= 1 && g <= 64) ? g : 4;
-  }();
-  if (variant == 1)
-    hipLaunchKernelGGL((cgemm_v3_presplit<4, 8>), grid, dim3(kV3Threads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb,
-                       2 * sa, 2 * sb, sc, rn);
-  else if (variant == 2)
-    hipLaunchKernelGGL((cgemm_v3_presplit<8, 4>), grid, dim3(kV3Threads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb,
-                       2 * sa, 2 * sb, sc, rn);
-  else if (variant == 3)
-    hipLaunchKernelGGL(cgemm_v4_presplit<false>, grid, dim3(kV3Threads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb,
-                       2 * sa, 2 * sb, sc, rn, group_rows);
-  else
-    hipLaunchKernelGGL(cgemm_v4_presplit<true>, grid, dim3(kV3Threads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb,
-                       2 * sa, 2 * sb, sc, rn, group_rows);
+  hipLaunchKernelGGL(cgemm_v4_presplit, grid, dim3(kV3Threads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb, 2 * sa,
+                     2 * sb, sc, rn);
   return hipGetLastError();
 }
 

@@ -130,18 +130,8 @@ hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const 
   std::sort(by_src.begin(), by_src.end(), [&](int x, int y) { return p.perm[x] < p.perm[y]; });
   // tiles of 2^12 elements (33 KiB of LDS) with runs of 2^6 elements (512 bytes) on both sides:
   // on 2^30-element permutes 5.1-5.5 TB/s, 2-5% above 2^11 tiles with 256-byte runs except for
-  // the identity, and 15% above 2^10 tiles.  QFMI_PERM_TILE and QFMI_PERM_RUN override them
-  // (comparison runs).
-  static const int tile_bits = [] {
-    const char* e = getenv("QFMI_PERM_TILE");
-    const int v = e ? atoi(e) : kPermMaxTile;
-    return (v >= 6 && v <= kPermMaxTile) ? v : kPermMaxTile;
-  }();
-  static const int run_bits = [] {
-    const char* e = getenv("QFMI_PERM_RUN");
-    const int v = e ? atoi(e) : 6;
-    return (v >= 1 && v <= 6) ? v : 6;
-  }();
+  // the identity, and 15% above 2^10 tiles
+  constexpr int tile_bits = kPermMaxTile, run_bits = 6;
   const int target = std::min(b, tile_bits);
   const int r = std::min(b, run_bits), w = std::min(b, run_bits);
   std::vector<char> in_tile(b, 0);

@@ -162,6 +162,7 @@ struct qf_plan {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph_obj = nullptr;
   std::vector<int64_t> graph_key;
+  int64_t graph_launches = 0;  // hipGraphLaunch calls made for this plan
   // backward plans: world-line environments and per-step scratch
   bool backward = false;
   size_t wl_elems = 0;
@@ -174,6 +175,10 @@ struct qf_plan {
   bool renorm = false;
   size_t off_scales = 0;
   std::vector<NodeScale> scale_init;
+  // qf_plan_info_get's result: fixed once the plan is laid out, computed on the first call
+  // (flops_next_slice simulates the reuse schedule over up to 4096 slices)
+  mutable bool info_ready = false;
+  mutable qf_plan_info info_cache{};
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -568,12 +573,7 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     st.k_bits = (int)K.size();
     st.m_bits = xf;
     st.n_bits = yf;
-    // QFMI_NO_PRESPLIT=1 keeps the split in the GEMM's LDS staging (comparison runs)
-    static const bool no_presplit = [] {
-      const char* e = std::getenv("QFMI_NO_PRESPLIT");
-      return e && e[0] == '1';
-    }();
-    st.presplit = p->precision == QF_BF16X3 && !p->backward && !no_presplit &&
+    st.presplit = p->precision == QF_BF16X3 && !p->backward &&
                   cgemm_presplit_fits((int64_t)1 << xf, (int64_t)1 << yf, (int64_t)1 << K.size());
     if (st.presplit) {
       for (Operand* op : {&st.A, &st.B}) {
@@ -782,6 +782,10 @@ qf_status qf_plan_step_info(const qf_plan* p, int i, qf_step_info* out) {
 
 qf_status qf_plan_info_get(const qf_plan* p, qf_plan_info* out) {
   if (!p || !out) return QF_ERR_ARG;
+  if (p->info_ready) {
+    *out = p->info_cache;
+    return QF_OK;
+  }
   std::memset(out, 0, sizeof(*out));
   out->n_slices = (int64_t)1 << p->total_cut_bits;
   out->n_open = (int)p->open.size();
@@ -802,6 +806,8 @@ qf_status qf_plan_info_get(const qf_plan* p, qf_plan_info* out) {
     if (v == GEMM_SKINNY || v == GEMM_SPLITK || v == GEMM_SIMT) continue;
     out->mfma_flops_per_slice += st.flops * (p->precision == QF_BF16X3 ? 3.0 : 1.0);
   }
+  p->info_cache = *out;
+  p->info_ready = true;
   return QF_OK;
 }
 
@@ -1102,21 +1108,29 @@ static qf_status enqueue_group(qf_plan* p, const uint8_t* bits_dev, int64_t s_be
   return QF_OK;
 }
 
-static qf_status amplitudes_batched(qf_plan* p, int n_batch, const uint8_t* bits_dev, int64_t s_begin, int64_t s_end,
-                                    double* out_dev) {
+// All groups of one call: the chain counter is reset, then every group runs the same launch
+// sequence (each reads the counter, runs its G chains and advances the counter on the device).
+static qf_status enqueue_call(qf_plan* p, int n_batch, const uint8_t* bits_dev, int64_t s_begin, int64_t s_end,
+                              double* out_dev, bool timed_ok) {
   qf_ctx* c = p->ctx;
   const int64_t s_range = s_end - s_begin;
   const int64_t n_chains = (int64_t)n_batch * s_range;
   const int64_t groups = (n_chains + p->G - 1) / p->G;
-  int64_t* chain0 = reinterpret_cast<int64_t*>(c->ws + 8);
-  QF_HIP(c, launch_chain_counter(c->stream, chain0, 0, 0));
-  if (!(p->graph && c->stream)) {
-    for (int64_t g = 0; g < groups; ++g) {
-      qf_status e = enqueue_group(p, bits_dev, s_begin, s_range, n_chains, out_dev, true);
-      if (e != QF_OK) return e;
-    }
-    return QF_OK;
+  QF_HIP(c, launch_chain_counter(c->stream, reinterpret_cast<int64_t*>(c->ws + 8), 0, 0));
+  for (int64_t g = 0; g < groups; ++g) {
+    qf_status e = enqueue_group(p, bits_dev, s_begin, s_range, n_chains, out_dev, timed_ok);
+    if (e != QF_OK) return e;
   }
+  return QF_OK;
+}
+
+// Batched plans.  With QF_PLAN_GRAPH the whole call (counter reset and every group) is captured
+// once into a hipGraph, keyed on the call's buffers, batch and slice range, and each call with
+// the same key is one hipGraphLaunch; otherwise the launches are enqueued directly.
+static qf_status amplitudes_batched(qf_plan* p, int n_batch, const uint8_t* bits_dev, int64_t s_begin, int64_t s_end,
+                                    double* out_dev) {
+  qf_ctx* c = p->ctx;
+  if (!(p->graph && c->stream)) return enqueue_call(p, n_batch, bits_dev, s_begin, s_end, out_dev, true);
   const std::vector<int64_t> key = {(int64_t)(uintptr_t)c->ws, (int64_t)(uintptr_t)bits_dev,
                                     (int64_t)(uintptr_t)out_dev, n_batch, s_begin, s_end,
                                     (int64_t)(uintptr_t)c->stream};
@@ -1129,7 +1143,7 @@ static qf_status amplitudes_batched(qf_plan* p, int n_batch, const uint8_t* bits
       p->graph_obj = nullptr;
     }
     QF_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    qf_status e = enqueue_group(p, bits_dev, s_begin, s_range, n_chains, out_dev, false);
+    qf_status e = enqueue_call(p, n_batch, bits_dev, s_begin, s_end, out_dev, false);
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(c->stream, &graph);
     if (e != QF_OK) {
@@ -1147,7 +1161,21 @@ static qf_status amplitudes_batched(qf_plan* p, int n_batch, const uint8_t* bits
     p->graph_obj = graph;
     p->graph_key = key;
   }
-  for (int64_t g = 0; g < groups; ++g) QF_HIP(c, hipGraphLaunch(p->gexec, c->stream));
+  QF_HIP(c, hipGraphLaunch(p->gexec, c->stream));
+  ++p->graph_launches;
+  return QF_OK;
+}
+
+extern "C" qf_status qf_plan_graph_info(const qf_plan* p, int64_t* launches, int64_t* nodes) {
+  if (!p || !launches || !nodes) return QF_ERR_ARG;
+  *launches = p->graph_launches;
+  *nodes = 0;
+  if (p->graph_obj) {
+    size_t count = 0;
+    const hipError_t e = hipGraphGetNodes(p->graph_obj, nullptr, &count);
+    if (e != hipSuccess) return p->ctx ? hip_fail(p->ctx, e, "hipGraphGetNodes") : QF_ERR_HIP;
+    *nodes = (int64_t)count;
+  }
   return QF_OK;
 }
 

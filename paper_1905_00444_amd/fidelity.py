@@ -1,4 +1,4 @@
-"""Noisy simulation by partial path sums (paper Sec. III-D).
+"""Noisy simulation by partial path sums (paper Sec. III-C).
 
 The slices of a sliced contraction are the paper's paths: for random circuits they are close
 to orthogonal and of equal weight, so summing a fraction f of them yields amplitudes a_f whose

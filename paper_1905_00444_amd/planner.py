@@ -1,4 +1,4 @@
-"""Automatic choice of cuts and contraction order for grid circuits (paper Sec. III-E).
+"""Automatic choice of cuts and contraction order for grid circuits (paper Sec. III-D).
 
 Finding the best cuts and order is NP-hard in general; for planar grids the paper splits the
 circuit into pieces with a small shared boundary, cuts bonds on that boundary, and prefers a few

@@ -1,4 +1,4 @@
-"""Noisy simulation by partial path sums (paper Sec. III-D): the oracle's per-path states are
+"""Noisy simulation by partial path sums (paper Sec. III-C): the oracle's per-path states are
 pinned against the full evolution and the tensor-network slices, the fidelity ~ f property is
 checked on the oracle, and the host bookkeeping of the package's fidelity module is checked on
 closed forms."""

@@ -89,12 +89,18 @@ def test_graph_replays_match_eager(gctx):
     bits_t = torch.from_numpy(bits).to(gctx.device)
     with torch.cuda.stream(gctx.stream):
         out = torch.zeros((4, 4), dtype=torch.complex128, device=gctx.device)
+    n_chains = 4 * graph.info()["n_slices"]
+    assert n_chains // 4 >= 8  # several groups of 4 chains per call
     for rep in range(4):
         with torch.cuda.stream(gctx.stream):
             out.zero_()
         graph.amplitudes(bits_t, out=out)  # same pointers every time: the captured graph is replayed
         gctx.synchronize()
         assert np.array_equal(out.cpu().numpy(), ref), rep
+        # the whole call, every group of 4 chains, is one graph launch
+        launches, nodes = graph.graph_info()
+        assert launches == rep + 1
+        assert nodes > n_chains // 4
         # eager work between replays
         eager.amplitudes(bits)
         gctx.synchronize()

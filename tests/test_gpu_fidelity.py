@@ -1,4 +1,4 @@
-"""Partial path sums through the HIP path (paper Sec. III-D): parity with the oracle's per-path
+"""Partial path sums through the HIP path (paper Sec. III-C): parity with the oracle's per-path
 states, and the fidelity of a quarter of the paths measured on all 2^16 amplitudes."""
 import numpy as np
 import pytest

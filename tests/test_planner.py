@@ -1,4 +1,4 @@
-"""Automatic cut and order search (paper Sec. III-E): its plans are valid and exact (oracle),
+"""Automatic cut and order search (paper Sec. III-D): its plans are valid and exact (oracle),
 its time model's reuse rule and sizes agree with the library's own bookkeeping, and on the 7x7
 (1+40+1) workload it finds a plan at least as good as the hand-built one."""
 import ctypes as C
