@@ -261,12 +261,19 @@ qf_status qf_split_bf16(qf_ctx* ctx, const void* src, void* dst, int nbits);
 
 /* Split-BF16 complex GEMM on operands produced by qf_split_bf16 (A of M x K, B of N x K
  * elements, row-major, K contiguous): C[m][n] = sum_k A[m][k] B[n][k] as
- * hi*hi + hi*lo + lo*hi with FP32 accumulation, C complex64 row-major.  Needs powers of two
- * with M >= 256, N >= 128, K >= 16 (QF_ERR_UNSUPPORTED otherwise). */
+ * hi*hi + hi*lo + lo*hi with FP32 accumulation, C complex64 row-major: the "G" of the paper's
+ * transpose-GEMM-transpose contraction (Sec. III-E), which ran as FP32 complex GEMM; the paper
+ * weighs reduced-precision inputs against the range its amplitudes need (same section), and the
+ * two BF16 terms per operand keep FP32's exponent range and about 16 bits of mantissa.
+ * lda / ldb: 32-bit words between consecutive rows of each plane (0 = K, dense); each operand
+ * is its hi plane then its lo plane, rows * ld words each (the layout the plan's permutes
+ * write, with padded rows for long K).
+ * Needs powers of two with M >= 256, N >= 128, K >= 16 (QF_ERR_UNSUPPORTED otherwise) and
+ * ld >= K, a multiple of 4 (QF_ERR_ARG).  Device pointers; the caller owns every buffer. */
 qf_status qf_cgemm_presplit(qf_ctx* ctx, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
-                            void* C);
+                            void* C, int64_t lda, int64_t ldb);
 qf_status qf_time_cgemm_presplit(qf_ctx* ctx, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
-                                 void* C, int reps, float* ms);
+                                 void* C, int64_t lda, int64_t ldb, int reps, float* ms);
 
 /* Time one launch configuration of qf_cgemm / qf_permute with HIP events on the context's
  * stream: runs `reps` launches and returns the average milliseconds per launch in *ms.

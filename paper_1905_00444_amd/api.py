@@ -297,20 +297,22 @@ def split_bf16(ctx: Context, x, out=None):
     return out
 
 
-def cgemm_presplit(ctx: Context, As, Bs, M: int, N: int, K: int, out=None):
-    """C = A B^T from split operands (see split_bf16)."""
+def cgemm_presplit(ctx: Context, As, Bs, M: int, N: int, K: int, out=None, lda: int = 0, ldb: int = 0):
+    """C = A B^T from split operands (see split_bf16); lda / ldb: words between rows of a plane
+    (0: dense, K)."""
     torch = _torch()
     if out is None:
         out = torch.empty((M, N), dtype=torch.complex64, device=As.device)
     check(ctx.lib.qf_cgemm_presplit(ctx.h, M, N, K, C.c_void_p(As.data_ptr()), C.c_void_p(Bs.data_ptr()),
-                                    C.c_void_p(out.data_ptr())), ctx.h)
+                                    C.c_void_p(out.data_ptr()), lda, ldb), ctx.h)
     return out
 
 
-def time_cgemm_presplit(ctx: Context, As, Bs, C_out, M: int, N: int, K: int, reps: int = 5) -> float:
+def time_cgemm_presplit(ctx: Context, As, Bs, C_out, M: int, N: int, K: int, reps: int = 5, lda: int = 0,
+                        ldb: int = 0) -> float:
     ms = C.c_float()
     check(ctx.lib.qf_time_cgemm_presplit(ctx.h, M, N, K, C.c_void_p(As.data_ptr()), C.c_void_p(Bs.data_ptr()),
-                                         C.c_void_p(C_out.data_ptr()), reps, C.byref(ms)), ctx.h)
+                                         C.c_void_p(C_out.data_ptr()), lda, ldb, reps, C.byref(ms)), ctx.h)
     return ms.value
 
 

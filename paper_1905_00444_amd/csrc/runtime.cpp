@@ -1503,25 +1503,31 @@ qf_status qf_split_bf16(qf_ctx* c, const void* src, void* dst, int nbits) {
   return QF_OK;
 }
 
-qf_status qf_cgemm_presplit(qf_ctx* c, int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C) {
+qf_status qf_cgemm_presplit(qf_ctx* c, int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C,
+                            int64_t lda, int64_t ldb) {
   if (!c || !A || !B || !C) return fail(c, QF_ERR_ARG, "qf_cgemm_presplit: null pointer");
   if (!cgemm_presplit_fits(M, N, K))
     return fail(c, QF_ERR_UNSUPPORTED, "qf_cgemm_presplit needs powers of two with M >= 256, N >= 128, K >= 16");
-  QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, reinterpret_cast<float2*>(C), 1, M * K, N * K, M * N));
+  if (lda == 0) lda = K;
+  if (ldb == 0) ldb = K;
+  if (lda < K || ldb < K || (lda & 3) || (ldb & 3))
+    return fail(c, QF_ERR_ARG, "qf_cgemm_presplit: row pitches must be >= K and multiples of 4 words");
+  QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, reinterpret_cast<float2*>(C), 1, M * lda, N * ldb, M * N,
+                                  Renorm{}, lda, ldb));
   return QF_OK;
 }
 
 qf_status qf_time_cgemm_presplit(qf_ctx* c, int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C,
-                                 int reps, float* ms) {
+                                 int64_t lda, int64_t ldb, int reps, float* ms) {
   if (!c || !ms || reps < 1) return QF_ERR_ARG;
-  qf_status st = qf_cgemm_presplit(c, M, N, K, A, B, C);
+  qf_status st = qf_cgemm_presplit(c, M, N, K, A, B, C, lda, ldb);
   if (st != QF_OK) return st;
   hipEvent_t e0, e1;
   QF_HIP(c, hipEventCreate(&e0));
   QF_HIP(c, hipEventCreate(&e1));
   QF_HIP(c, hipEventRecord(e0, c->stream));
   for (int i = 0; i < reps; ++i) {
-    st = qf_cgemm_presplit(c, M, N, K, A, B, C);
+    st = qf_cgemm_presplit(c, M, N, K, A, B, C, lda, ldb);
     if (st != QF_OK) return st;
   }
   QF_HIP(c, hipEventRecord(e1, c->stream));

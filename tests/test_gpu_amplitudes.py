@@ -335,24 +335,6 @@ def test_11x11_d24_scaled_product_circuit_full_shape(ctx, precision):
         assert rel_err(flat.cpu().numpy()[0], ref) > 0.5  # underflows at true scale
 
 
-def test_7x7_d32_full_amplitudes_follow_porter_thomas(ctx):
-    """Whole amplitudes (all 16 paths) of 256 bitstrings of the 49-qubit (1+32+1) circuit: the
-    paper's scale (mean |a|^2 = 2^-49, about 1e-15) and the Porter-Thomas statistics of a chaotic
-    circuit (N p ~ Exp(1): mean 1, second moment 2), within 4 standard errors for 256 samples."""
-    from oracle.metrics import porter_thomas
-    _say("7x7 d32 full amplitudes, Porter-Thomas")
-    c = generate(7, 7, 32, 0)
-    plan, _ = plan_7x7(c, 32)
-    bits = random_bitstrings(4, 49, 3)
-    got = _amps(ctx, c, plan, bits, "bf16x3")
-    assert got.shape == (4, 64)
-    m1, m2, ks = porter_thomas(got, 49)
-    assert abs(m1 - 1.0) <= 0.25, m1
-    assert 1.0 <= m2 <= 3.2, m2
-    assert ks <= 0.12, ks
-    assert 0.5e-15 < np.mean(np.abs(got) ** 2) < 3e-15
-
-
 def test_one_call_amplitudes_function():
     import torch
     from paper_1905_00444_amd import amplitudes

@@ -268,3 +268,94 @@ def test_cgemm_tall_batched_and_rejects_other_shapes(ctx):
     with pytest.raises(RuntimeError):
         cgemm(ctx, torch.zeros((4096, 32), dtype=torch.complex64, device="cuda"),
               torch.zeros((4, 32), dtype=torch.complex64, device="cuda"), "bf16x3", variant="tall")
+
+
+def _padded_planes(S, rows, K, ld):
+    """Split planes (hi then lo, rows x K words each) copied into rows of ld words; the pad words
+    hold a NaN pattern in both bfloat16 halves, so any read of them would poison the result."""
+    import torch
+    P = torch.full((2, rows, ld), 0x7FC07FC0, dtype=torch.int32, device=S.device)
+    P[:, :, :K] = S.view(2, rows, K)
+    return P
+
+
+@pytest.mark.parametrize("M,N,K", [(512, 256, 8192), (512, 256, 32768), (256, 512, 16384)])
+def test_cgemm_presplit_padded_rows_match_numpy(ctx, M, N, K):
+    """The padded-row form the plan uses for K >= 2^13 (rows K + 64 words apart), on random
+    operands, element-wise against numpy complex128."""
+    import torch
+    from paper_1905_00444_amd import split_bf16, cgemm_presplit
+    _say(f"cgemm presplit padded {M}x{N}x{K}")
+    rng = np.random.default_rng(M + 2 * N + K)
+    A = _rand_c64(rng, (M, K))
+    B = _rand_c64(rng, (N, K))
+    ref = A.astype(np.complex128) @ B.astype(np.complex128).T
+    bound = np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64).T
+    ld = K + 64
+    Ap = _padded_planes(split_bf16(ctx, torch.from_numpy(A).cuda().reshape(-1)), M, K, ld)
+    Bp = _padded_planes(split_bf16(ctx, torch.from_numpy(B).cuda().reshape(-1)), N, K, ld)
+    Cg = cgemm_presplit(ctx, Ap, Bp, M, N, K, lda=ld, ldb=ld)
+    torch.cuda.synchronize()
+    got = Cg.cpu().numpy().astype(np.complex128)
+    assert np.all(np.isfinite(got))
+    err = np.max(np.abs(got - ref) / bound)
+    assert err <= TOL["bf16x3"], err
+
+
+def test_cgemm_presplit_full_size_sampled_outputs(ctx):
+    """The benchmark's largest contraction shape, 2^15 x 2^15 x 2^15 complex, in the padded-row
+    layout, on seeded random normal operands: 512 sampled outputs against numpy complex128 sums
+    of the same operands' rows."""
+    import torch
+    from paper_1905_00444_amd import split_bf16, cgemm_presplit
+    M = N = K = 1 << 15
+    ld = K + 64
+    _say("cgemm presplit full size 2^15 cubed")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(15)
+    A = torch.randn(M * K, dtype=torch.complex64, device="cuda", generator=g)
+    B = torch.randn(N * K, dtype=torch.complex64, device="cuda", generator=g)
+    Ap = _padded_planes(split_bf16(ctx, A), M, K, ld)
+    Bp = _padded_planes(split_bf16(ctx, B), N, K, ld)
+    torch.cuda.synchronize()
+    Cg = cgemm_presplit(ctx, Ap, Bp, M, N, K, lda=ld, ldb=ld)
+    torch.cuda.synchronize()
+    del Ap, Bp
+    rng = np.random.default_rng(16)
+    ms = rng.integers(0, M, 512)
+    ns = rng.integers(0, N, 512)
+    # every tile corner and edge of the 256 x 128 blocks is among the samples too
+    ms[:4] = [0, 255, 256, M - 1]
+    ns[:4] = [0, 127, 128, N - 1]
+    ar = A.view(M, K)[torch.from_numpy(ms).cuda()].cpu().numpy().astype(np.complex128)
+    br = B.view(N, K)[torch.from_numpy(ns).cuda()].cpu().numpy().astype(np.complex128)
+    got = Cg[torch.from_numpy(ms).cuda(), torch.from_numpy(ns).cuda()].cpu().numpy().astype(np.complex128)
+    ref = np.sum(ar * br, axis=1)
+    bound = np.sum(np.abs(ar) * np.abs(br), axis=1)
+    err = np.max(np.abs(got - ref) / bound)
+    assert err <= TOL["bf16x3"], err
+
+
+def test_permute_2_30_elements_sampled_bit_exact(ctx):
+    """A 2^30-element (8 GiB) bit permutation, byte offsets well past 2^32: 2^16 sampled
+    destination elements equal the source elements that numpy's index arithmetic names."""
+    import torch
+    from paper_1905_00444_amd import permute
+    b = 30
+    _say("permute 2^30 elements")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(30)
+    src = torch.randn(1 << b, dtype=torch.complex64, device="cuda", generator=g)
+    dst = torch.empty_like(src)
+    rng = np.random.default_rng(30)
+    perm = [int(x) for x in rng.permutation(b)]
+    permute(ctx, src, dst, perm)
+    torch.cuda.synchronize()
+    j = rng.integers(0, 1 << b, 1 << 16, dtype=np.int64)
+    j[:2] = [0, (1 << b) - 1]
+    idx = np.zeros_like(j)
+    for i, p in enumerate(perm):
+        idx |= ((j >> i) & 1) << p
+    got = dst[torch.from_numpy(j).cuda()].cpu().numpy()
+    want = src[torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
