@@ -28,6 +28,13 @@ def _say(msg):
     print(msg, flush=True)
 
 
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated yet (tests/golden/make_goldens.py)")
+    return np.load(path)
+
+
 @pytest.fixture(scope="module")
 def ctx():
     import torch
@@ -40,7 +47,7 @@ def ctx():
 def test_7x7_d40_slice_vs_fp64_oracle(ctx, precision):
     import torch
     from paper_1905_00444_amd import Circuit, Plan
-    g = np.load(os.path.join(GOLDEN, "c4_slice.npz"))
+    g = _golden("c4_slice.npz")
     circ = generate(7, 7, 40, 0)
     plan, _ = plan_7x7(circ, 40)
     bits = random_bitstrings(64, 49, 1)[:1]
@@ -63,7 +70,7 @@ def test_70_qubit_hand_plan_path_sums_vs_fp64_oracle():
     from paper_1905_00444_amd import Context, Circuit, Plan
     _say("70 qubits, hand plan, 4 bitstrings x 256 slices vs FP64 oracle")
     ctx = Context(0, stream=torch.cuda.Stream())
-    g = np.load(os.path.join(GOLDEN, "c5_amplitudes.npz"))
+    g = _golden("c5_amplitudes.npz")
     circ = generate(8, 9, 24, 0, C5_REMOVED)
     bits = random_bitstrings(16, 70, 1)
     assert np.array_equal(g["bits"], bits)
@@ -83,7 +90,7 @@ def test_70_qubit_searched_plan_vs_fp64_oracle(ctx, precision):
     import torch
     from paper_1905_00444_amd import Circuit, Plan, planner
     _say(f"70 qubits, searched plan, 16 amplitudes vs FP64 oracle, {precision}")
-    g = np.load(os.path.join(GOLDEN, "c5_amplitudes.npz"))
+    g = _golden("c5_amplitudes.npz")
     circ = generate(8, 9, 24, 0, C5_REMOVED)
     text = circ.to_text()
     best = planner.search(text, 27)
@@ -100,7 +107,7 @@ def test_6x6_d24_gradient_vs_fp64_finite_differences(ctx):
     import torch
     from paper_1905_00444_amd import Circuit, Plan
     _say("6x6 d24 gradient vs FP64 finite differences")
-    g = np.load(os.path.join(GOLDEN, "c2_grad.npz"))
+    g = _golden("c2_grad.npz")
     circ = generate(6, 6, 24, 0)
     bits = random_bitstrings(64, 36, 1)
     assert np.array_equal(g["bits"], bits)
