@@ -29,7 +29,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--slices", type=int, default=6, help="slices per step (fidelity slices/1024)")
-    ap.add_argument("--fp32-steps", type=int, default=1)
+    ap.add_argument("--fp32-steps", type=int, default=3)
+    ap.add_argument("--fp16-steps", type=int, default=3)
+    ap.add_argument("--whole-prefixes", type=int, default=1,
+                    help="prefixes whose whole path sum (every contributing slice) is timed in split-BF16")
     ap.add_argument("--c5-slices", type=int, default=256,
                     help="8x9-d24: slices per bitstring of the hand plan's 256 (a multiple of 16 or all)")
     ap.add_argument("--cpu-reps", type=int, default=10, help="prefixes in the CPU oracle sample")
@@ -325,38 +328,75 @@ def cpu_sample_steps(plan, pb, max_bits=25):
     return sel
 
 
-def cpu_baseline(circ, plan, pb, bits, flops_per_step, n_amp, reps):
-    """Time the FP64 oracle on a bounded sample of the same workload (the plan's steps whose
-    tensors stay at or below 2^25 elements, slice 0, `reps` prefixes) and scale its flop rate
-    to amplitudes/s of one bench step."""
+def host_cores():
+    """(physical cores from lscpu, logical CPUs from os.cpu_count())."""
+    import subprocess
+    phys = None
+    try:
+        out = subprocess.run(["lscpu", "-p=core,socket"], capture_output=True, text=True, timeout=10).stdout
+        phys = len({ln for ln in out.splitlines() if ln and not ln.startswith("#")})
+    except Exception:
+        pass
+    return phys, os.cpu_count()
+
+
+def cpu_baseline(circ, plan, pb, bits, step_info, flops_per_step, n_amp, reps):
+    """Time the FP64 oracle on a bounded sample of the same workload and scale to one bench step:
+    (1) the plan's steps whose tensors stay at or below 2^25 elements, slice 0, `reps` prefixes
+    (tn.partial_contract); (2) the oracle's pairwise contraction (tn._contract, numpy tensordot in
+    complex128) on one 2^13 x 2^13 x 2^13 complex product, the form of the plan's large steps.  A
+    bench step's flops split into the small-step class (1) and the rest (2) as in one slice of the
+    plan; its time is each class's flops over that class's measured rate."""
+    import numpy as np
     from oracle import tn
     text = circ.to_text()
     sel = cpu_sample_steps(plan, pb)
-    fl = 0.0
+    fl_small = 0.0
     for i in sel:
         (a, b), vc = plan["steps"][i], pb.sizes()[i]
         va, vb = pb.bits_of(pb.members[a]), pb.bits_of(pb.members[b])
-        fl += 8 * 2.0 ** ((va + vb + vc) / 2)
+        fl_small += 8 * 2.0 ** ((va + vb + vc) / 2)
     t0 = time.perf_counter()
     for r in range(reps):
         tn.partial_contract(text, bits[r], plan, 0, subset=sel)
-    dt = time.perf_counter() - t0
-    fl *= reps
-    rate = fl / dt
+    dt_small = time.perf_counter() - t0
+    rate_small = fl_small * reps / dt_small
+    # dominant class: A[m bits | k bits] x B[k bits | n bits] over the k bits, 2^13 each
+    h = 13
+    rng = np.random.default_rng(0)
+    la = [("m", i) for i in range(h)] + [("k", i) for i in range(h)]
+    lb = [("k", i) for i in range(h)] + [("n", i) for i in range(h)]
+    a = (rng.standard_normal(2 ** (2 * h)) + 1j * rng.standard_normal(2 ** (2 * h))).reshape((2,) * (2 * h))
+    b = (rng.standard_normal(2 ** (2 * h)) + 1j * rng.standard_normal(2 ** (2 * h))).reshape((2,) * (2 * h))
+    t0 = time.perf_counter()
+    tn._contract(a, la, b, lb)
+    dt_big = time.perf_counter() - t0
+    fl_big = 8.0 * 2.0 ** (3 * h)
+    rate_big = fl_big / dt_big
+    # flops of one slice of the plan by class (all steps, no reuse)
+    slice_small = sum(st["flops"] for k, st in enumerate(step_info) if k in set(sel))
+    slice_all = sum(st["flops"] for st in step_info)
+    f_small = slice_small / slice_all
+    t_step = flops_per_step * (f_small / rate_small + (1.0 - f_small) / rate_big)
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
-        cores = os.cpu_count()
-    return {"value": n_amp * rate / flops_per_step, "unit": "amplitudes/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 numpy oracle on {len(sel)} of the {len(plan['steps'])} contractions of the 7x7 (1+40+1) "
-                      f"plan (those with tensors <= 2^25 elements), slice 0, {reps} prefixes: {fl:.3e} flop in "
-                      f"{dt:.1f} s = {rate / 1e9:.1f} GFLOP/s, scaled by flops to one step ({flops_per_step:.3e} "
-                      f"flop, {n_amp} amplitudes)",
-            "fp64_gflops": rate / 1e9}
+        threads = None
+    phys, logical = host_cores()
+    return {"value": n_amp / t_step, "unit": "amplitudes/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 numpy oracle: (1) {len(sel)} of the {len(plan['steps'])} contractions of the 7x7 "
+                      f"(1+40+1) plan (tensors <= 2^25 elements), slice 0, {reps} prefixes: "
+                      f"{fl_small * reps:.3e} flop in {dt_small:.1f} s = {rate_small / 1e9:.1f} GFLOP/s; (2) the "
+                      f"oracle's contraction on one 2^13-cubed complex product (the large steps' form): "
+                      f"{fl_big:.3e} flop in {dt_big:.1f} s = {rate_big / 1e9:.1f} GFLOP/s; one step "
+                      f"({flops_per_step:.3e} flop, {n_amp} amplitudes) at {100 * f_small:.2f}% class (1) and the "
+                      f"rest class (2) flops",
+            "fp64_gflops_small_steps": rate_small / 1e9, "fp64_gflops_large_product": rate_big / 1e9,
+            "threads": threads, "physical_cores": phys, "os_cpu_count": logical}
 
 
-PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "cgemm_v4_presplit_7x7_d40.md")
+PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "cgemm_pingpong_presplit_7x7_d40.md")
 GEMM_SRC = [os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1905_00444_amd", "csrc", f)
             for f in ("cgemm_presplit.hip", "cgemm_common.h")]
 
@@ -399,7 +439,7 @@ def main():
     from paper_1905_00444_amd import Context, Circuit, Plan, profile_enable, profile_read, autotune
     from workloads.bitstrings import random_bitstrings
     from workloads.circuits import generate
-    from workloads.plans import plan_7x7
+    from workloads.plans import plan_7x7, nonvanishing_slices
 
     print("bench: building 7x7 (1+40+1) workload", file=sys.stderr, flush=True)
     circ = generate(7, 7, 40, 0)
@@ -407,32 +447,31 @@ def main():
     bits = random_bitstrings(64, 49, 1)
     ctx = Context(0)
     cobj = Circuit(ctx, circ.to_text())
-    plans = {p: Plan(ctx, cobj, plan, p) for p in ("bf16x3", "fp32")}
+    legs = [("bf16x3", args.steps), ("fp32", args.fp32_steps), ("fp16", args.fp16_steps)]
+    plans = {prec: Plan(ctx, cobj, plan, prec) for prec, k in legs if k > 0 or prec == "bf16x3"}
     info = plans["bf16x3"].info()
     S = args.slices
     n_amp = 2 ** info["n_open"]
     ctx.ensure_workspace(info["workspace_bytes"])
-    # the paths of each prefix: the first S slices not forced to zero by the gate pattern on the
-    # cut qubits (for this circuit 128 of the 1024 paths of a prefix can be nonzero)
-    from workloads.plans import nonvanishing_slices
-    n_free = len(nonvanishing_slices(circ, plan, bits[0], info["n_slices"]))
-    runs = []
-    for b in range(len(bits)):
-        sl = nonvanishing_slices(circ, plan, bits[b], S)
+
+    def runs_of(sl):
         r = []
         for x in sl:
             if r and r[-1][1] == x:
                 r[-1][1] = x + 1
             else:
                 r.append([x, x + 1])
-        runs.append(r)
+        return r
+
+    # the paths of each prefix: the first S slices not forced to zero by the gate pattern on the
+    # cut qubits (for this circuit 128 of the 1024 paths of a prefix can be nonzero)
+    n_free = len(nonvanishing_slices(circ, plan, bits[0], info["n_slices"]))
+    runs = [runs_of(nonvanishing_slices(circ, plan, bits[b], S)) for b in range(len(bits))]
     step_flops = [sum(plans["bf16x3"].flops(a, e) for a, e in r) for r in runs]
 
     if not args.no_autotune:
         # per-shape kernel choice for the plans' GEMMs (held in the context; untimed set-up)
-        for prec in ("bf16x3", "fp32"):
-            if prec == "fp32" and args.fp32_steps <= 0:
-                continue
+        for prec in plans:
             t0 = time.perf_counter()
             autotune(plans[prec])
             torch.cuda.synchronize()
@@ -445,21 +484,26 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    def run(prec, i):
+    def run(prec, i, rr=None):
         b = i % len(bits)
         out = None
-        for a, e in runs[b]:
+        for a, e in (rr if rr is not None else runs[b]):
             out = plans[prec].amplitudes(bits[b:b + 1], a, e, out=out)
         return out
 
     results = {}
-    for prec, steps in (("bf16x3", args.steps), ("fp32", args.fp32_steps)):
+    for prec, steps in legs:
         if steps <= 0:
             continue
-        for w in range(args.warmup):
-            run(prec, w)
+        if prec == "bf16x3":
+            for w in range(args.warmup):
+                run(prec, w)
+                torch.cuda.synchronize()
+                print(f"bench: warmup {prec} {w} done", file=sys.stderr, flush=True)
+        else:
+            # one slice: workspace, kernels and tuning choices in place before the timed steps
+            run(prec, 0, [[runs[0][0][0], runs[0][0][0] + 1]])
             torch.cuda.synchronize()
-            print(f"bench: warmup {prec} {w} done", file=sys.stderr, flush=True)
         profile_enable(ctx, True)
         profile_read(ctx, reset=True)
         torch.cuda.synchronize()
@@ -467,9 +511,8 @@ def main():
         amps = []
         for i in range(steps):
             amps.append(run(prec, i))
-            if prec == "bf16x3":
-                torch.cuda.synchronize()
-                print(f"bench: step {i} done", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            print(f"bench: {prec} step {i} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         gms, glaunch, gflops = profile_read(ctx, reset=True)
@@ -478,59 +521,85 @@ def main():
                          "gemm_ms": gms, "gemm_launches": glaunch, "gemm_flops": gflops}
         print(f"bench: {prec} {steps} steps in {dt:.2f} s", file=sys.stderr, flush=True)
 
+    from numpy.linalg import norm
+
+    def leg(prec):
+        r = results.get(prec)
+        if not r:
+            return None
+        fl = sum(step_flops[i % len(bits)] for i in range(r["steps"]))
+        return {"value": n_amp * r["steps"] / r["s"], "complex_tflops": fl / r["s"] / 1e12, "steps": r["steps"],
+                "ms_per_step": r["s"] / r["steps"] * 1e3}
+
+    def rel(prec):
+        # norm-wise difference from FP32 on the same prefixes (same steps)
+        a, f = results.get(prec), results.get("fp32")
+        if not a or not f:
+            return None
+        k = min(len(a["amps"]), len(f["amps"]))
+        den = norm(f["amps"][:k])
+        return float(norm(a["amps"][:k] - f["amps"][:k]) / den) if den > 0 else None
+
     bf = results["bf16x3"]
-    fp = results.get("fp32")
-    ms_step = bf["s"] / bf["steps"] * 1e3
-    value = n_amp * bf["steps"] / bf["s"]
+    main_leg = leg("bf16x3")
+    ms_step = main_leg["ms_per_step"]
+    value = main_leg["value"]
     flops_step = sum(step_flops[i % len(bits)] for i in range(bf["steps"])) / bf["steps"]
-    tflops = flops_step * bf["steps"] / bf["s"] / 1e12
-    fp_value = n_amp * fp["steps"] / fp["s"] if fp else None
-    fp_flops = sum(step_flops[i % len(bits)] for i in range(fp["steps"])) / fp["steps"] if fp else None
-    fp_tflops = fp_flops * fp["steps"] / fp["s"] / 1e12 if fp else None
-    # self-consistency of the two precisions on the same prefixes
-    bf_vs_fp = None
-    if fp:
-        from numpy.linalg import norm
-        k = min(len(fp["amps"]), len(bf["amps"]))
-        den = norm(fp["amps"][:k])
-        bf_vs_fp = float(norm(bf["amps"][:k] - fp["amps"][:k]) / den) if den > 0 else None
-        rec_norms = {"bf16x3": float(norm(bf["amps"][:k])), "fp32": float(den)}
     gemm_avg_ms = bf["gemm_ms"] / max(1, bf["gemm_launches"])
     per_launch = bf["gemm_flops"] / max(1, bf["gemm_launches"])
     achieved = per_launch / (gemm_avg_ms * 1e-3) / 1e12 if gemm_avg_ms > 0 else 0.0
     peak = PEAK_BF16 / 3.0
+    fp_leg = leg("fp32")
     rec = {
         "metric": "amplitudes/s and complex Tflop/s, 7x7 (1+40+1) RQC; split-BF16 vs FP32 at stated rel err",
-        "value": value, "unit": f"amplitudes/s ({S} paths per amplitude: fidelity {S}/{n_free} of the nonvanishing paths, {S}/1024 of all)",
+        "value": value,
+        "unit": f"amplitudes/s ({S} paths per amplitude: fidelity {S}/{n_free} of the paths that can be nonzero, "
+                f"{S}/1024 of all)",
         "n_gpus": 1, "steps": bf["steps"], "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3 (FP32 accumulate)",
         "data": "synthetic: seeded 7x7 (1+40+1) random circuit, seeded bitstring prefixes",
         "config": {"workload": "7x7 (1+40+1) RQC, bond 32, 2 cuts (1024 slices), 6 open qubits (64 amplitudes "
                                f"per prefix), {S} nonvanishing slices per step", "global_batch": n_amp,
                    "slices_per_step": S, "nonvanishing_slices_per_prefix": n_free, "parallelism": "single GPU"},
-        "complex_tflops": tflops,
-        "fp32": ({"value": fp_value, "complex_tflops": fp_tflops, "steps": fp["steps"],
-                  "ms_per_step": fp["s"] / fp["steps"] * 1e3} if fp else None),
-        "speedup_bf16x3_vs_fp32": value / fp_value if fp else None,
-        "rel_err_bf16x3_vs_fp32_same_prefixes": bf_vs_fp,
+        "complex_tflops": main_leg["complex_tflops"],
+        "fp32": fp_leg,
+        "fp16": leg("fp16"),
+        "speedup_bf16x3_vs_fp32": value / fp_leg["value"] if fp_leg else None,
+        "rel_err_vs_fp32_same_prefixes": {"bf16x3": rel("bf16x3"), "fp16": rel("fp16")},
         "flops_per_step": flops_step,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(),
                      "traffic_unit": "bytes per dispatch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": "cgemm_v4_presplit (split-BF16, operands split by the preceding permute) on the "
-                               "2^15 x 2^15 x 2^15 complex contractions",
+                     "kernel": "cgemm_pingpong_presplit (split-BF16, operands split by the preceding permute) on "
+                               "the 2^15 x 2^15 x 2^15 complex contractions",
                      "peak_note": "2516.6 TFLOP/s dense BF16 MFMA / 3 products per complex FP32 product; "
                                   "achieved counts algorithmic complex flops 8*M*N*K",
                      "launches": bf["gemm_launches"], "avg_ms": gemm_avg_ms},
     }
-    if fp:
-        rec["amplitude_norms_same_prefixes"] = rec_norms
+    if args.whole_prefixes > 0:
+        # whole amplitudes: every slice of the prefix that can be nonzero (the other 896 of the 1024
+        # paths are identically zero for this circuit), split-BF16
+        wr = [runs_of(nonvanishing_slices(circ, plan, bits[b], info["n_slices"])) for b in range(args.whole_prefixes)]
+        wfl = sum(plans["bf16x3"].flops(a, e) for r in wr for a, e in r)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in range(args.whole_prefixes):
+            run("bf16x3", b, wr[b])
+            torch.cuda.synchronize()
+            print(f"bench: whole path sum of prefix {b} done", file=sys.stderr, flush=True)
+        dt = time.perf_counter() - t0
+        rec["whole_amplitudes"] = {"value": n_amp * args.whole_prefixes / dt, "unit": "amplitudes/s",
+                                   "paths_per_amplitude": n_free, "prefixes": args.whole_prefixes, "seconds": dt,
+                                   "complex_tflops": wfl / dt / 1e12, "flops": wfl,
+                                   "note": "every path that can be nonzero (fidelity 1); the remaining "
+                                           f"{info['n_slices'] - n_free} slices are identically zero"}
     if not args.no_subcheck:
         print("bench: 4x4 (1+40+1) sub-check vs FP64 state vector", file=sys.stderr, flush=True)
         rec["rel_err_vs_fp64_4x4_d40"] = sub_check(ctx)
     if not args.no_cpu:
         print("bench: CPU oracle sample", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(circ, plan, pb, bits, flops_step, n_amp, args.cpu_reps)
+        rec["cpu_baseline"] = cpu_baseline(circ, plan, pb, bits, plans["bf16x3"].steps(), flops_step, n_amp,
+                                           args.cpu_reps)
     print(json.dumps(rec), flush=True)
     return 0
 

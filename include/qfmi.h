@@ -268,8 +268,8 @@ qf_status qf_split_bf16(qf_ctx* ctx, const void* src, void* dst, int nbits);
  * lda / ldb: 32-bit words between consecutive rows of each plane (0 = K, dense); each operand
  * is its hi plane then its lo plane, rows * ld words each (the layout the plan's permutes
  * write, with padded rows for long K).
- * Needs powers of two with M >= 256, N >= 128, K >= 16 (QF_ERR_UNSUPPORTED otherwise) and
- * ld >= K, a multiple of 4 (QF_ERR_ARG).  Device pointers; the caller owns every buffer. */
+ * Needs powers of two with M >= 256, N >= 128, 16 <= K <= 2^20 (QF_ERR_UNSUPPORTED otherwise)
+ * and K <= ld <= 2^21, a multiple of 4 (QF_ERR_ARG).  Device pointers; the caller owns every buffer. */
 qf_status qf_cgemm_presplit(qf_ctx* ctx, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
                             void* C, int64_t lda, int64_t ldb);
 qf_status qf_time_cgemm_presplit(qf_ctx* ctx, int64_t M, int64_t N, int64_t K, const void* A, const void* B,

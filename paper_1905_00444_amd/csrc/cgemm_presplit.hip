@@ -8,66 +8,78 @@ namespace qf {
 
 // Large shapes, split-BF16 on operands already split in HBM (hi and lo planes of bfloat16
 // complex numbers, [rows][K] each, written by the permute that precedes the GEMM).  A 256 x 128
-// complex block per workgroup, 8 waves, K-tiles of 16 complex; the operands travel HBM -> LDS
-// directly (global_load_lds_dwordx4: each lane
-// moves 16 bytes, one instruction fills 1 KiB = 16 rows x 64 bytes of one plane), through a
-// ring of 3 LDS stages: while tile kt is multiplied, tiles kt+1 and kt+2 are in flight.  Each
-// wave waits only for its own loads of tile kt (vmcnt), then one barrier makes every wave's
-// loads visible.  The four 16-byte chunks of a row are stored in the order c ^ ((row >> 1) & 3):
-// a 16-byte LDS read serves 8 lanes per pass, and the 8 rows (or 4 distinct B rows) that one pass
-// reads then land in 8 distinct 16-byte bank groups.
+// complex block per workgroup, 8 waves, K-tiles of 16 complex.  The operands travel HBM -> LDS
+// directly (buffer_load_dwordx4 ... lds: each lane moves 16 bytes, one instruction fills 1 KiB =
+// 16 rows x 64 bytes of one plane) through a ring of 3 LDS stages.  The four 16-byte chunks of a
+// row are stored in the order c ^ ((row >> 1) & 3): a 16-byte LDS read serves 8 lanes per pass,
+// and the 8 rows (or 4 distinct B rows) that one pass reads then land in 8 distinct 16-byte bank
+// groups.
+//
+// Schedule ("ping-pong"): the 8 waves form two groups of 4, one wave of each group per SIMD.  Each
+// wave alternates a read half (issue its share of the loads of tile t + 2, read its A and B
+// fragments of tile t from LDS into registers, expand B) and a multiply half (96 MFMAs from
+// registers, no memory instruction), with a workgroup barrier after each half.  Group 1 starts one
+// barrier later than group 0, so on every SIMD one wave multiplies while the other reads: the
+// matrix core is not left idle while a wave waits for LDS or expands its B fragments.
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
-typedef __attribute__((address_space(1))) void* gbl_ptr_t;
 
-constexpr int kV3Threads = 512;
-constexpr int kV3BM = 256, kV3BN = 128, kV3BK = 16;
-constexpr int kV3PlaneA = kV3BM * 64;                       // 16 KiB
-constexpr int kV3PlaneB = kV3BN * 64;                       // 8 KiB
-constexpr int kV3Stage = 2 * kV3PlaneA + 2 * kV3PlaneB;     // 48 KiB
-constexpr int kV3Stages = 3;
-constexpr int kV3LoadsPerWave = (kV3Stage / 1024) / (kV3Threads / 64);  // 6
+constexpr int kPsThreads = 512;
+constexpr int kPsBM = 256, kPsBN = 128, kPsBK = 16;
+constexpr int kPsPlaneA = kPsBM * 64;                      // 16 KiB
+constexpr int kPsPlaneB = kPsBN * 64;                      // 8 KiB
+constexpr int kPsStage = 2 * kPsPlaneA + 2 * kPsPlaneB;    // 48 KiB
+constexpr int kPsStages = 3;
+// Each wave owns a 128-row x 32-complex-column tile of the block (8 x 4 MFMA tiles of 16 x 16 real
+// outputs); group g holds rows 128 g .. 128 g + 127, wave w columns 32 (w mod 4) ...
+constexpr int kPsWI = 8, kPsWJ = 4;
+// Row tiles per raster group: after the XCD-aware reordering, the 32 workgroups that run together
+// on one XCD share 4 A panels and 8 B panels in that XCD's L2.
+constexpr int kPsGroupRows = 4;
+// Largest row pitch (32-bit words) of an operand plane: the loads address a block's 256-row panel
+// with 32-bit byte offsets.
+constexpr int64_t kPsMaxLd = (int64_t)1 << 21;
 
-__device__ __forceinline__ void v3_issue(char* stage, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
-                                         const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl,
-                                         int64_t lda, int64_t ldb, int64_t k0, int wave, int lane) {
-  const int r = lane >> 2, pos = lane & 3;
-  const int c = pos ^ ((r >> 1) & 3);
-#pragma unroll
-  for (int t = 0; t < kV3LoadsPerWave; ++t) {
-    const int q = wave + 8 * t;  // 1 KiB chunk of the stage: 0..31 A (hi 0..15, lo 16..31), 32..47 B
-    const uint32_t* src;
-    int off;
-    if (q < 32) {
-      const int plane = q >> 4, r0 = (q & 15) * 16;
-      src = (plane ? Al : Ah) + (int64_t)(r0 + r) * lda + k0 + 4 * c;
-      off = plane * kV3PlaneA + r0 * 64;
-    } else {
-      const int qq = q - 32, plane = qq >> 3, r0 = (qq & 7) * 16;
-      src = (plane ? Bl : Bh) + (int64_t)(r0 + r) * ldb + k0 + 4 * c;
-      off = 2 * kV3PlaneA + plane * kV3PlaneB + r0 * 64;
-    }
-    __builtin_amdgcn_global_load_lds((gbl_ptr_t)src, (lds_ptr_t)(stage + off), 16, 0, 0);
-  }
+// One tile's loads of one wave: 6 chunks of 1 KiB (chunks w, w + 8, ..., w + 40 of a stage): A hi
+// rows 16 w and 16 (w + 8), the same A lo rows, B hi and B lo rows 16 w.
+struct PsLoader {
+  __amdgpu_buffer_rsrc_t ah, al, bh, bl;  // the block's 256-row (128-row) panels of each plane
+  int va, vb;                             // lane offset within a chunk: row lane / 4, swizzled column
+  int ra0, ra1, rb;                       // byte offsets of the wave's chunk rows within a panel
+  int la0, la1, lb;                       // LDS offsets of the chunks within a stage
+};
+
+__device__ __forceinline__ void ps_issue(const PsLoader& L, char* stage, int kbytes) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.ah, (lds_ptr_t)(stage + L.la0), 16, L.va, L.ra0 + kbytes, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.ah, (lds_ptr_t)(stage + L.la1), 16, L.va, L.ra1 + kbytes, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.al, (lds_ptr_t)(stage + kPsPlaneA + L.la0), 16, L.va, L.ra0 + kbytes,
+                                           0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.al, (lds_ptr_t)(stage + kPsPlaneA + L.la1), 16, L.va, L.ra1 + kbytes,
+                                           0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.bh, (lds_ptr_t)(stage + L.lb), 16, L.vb, L.rb + kbytes, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.bl, (lds_ptr_t)(stage + kPsPlaneB + L.lb), 16, L.vb, L.rb + kbytes, 0,
+                                           0);
 }
 
-// Each wave owns a 128-row x 32-complex-column tile of the block (8 x 4 MFMA tiles of 16 x 16
-// real outputs; the 8 waves tile the block 2 x 4).  Per K-tile a wave reads its B fragments once
-// after the barrier (expanding each packed complex into the real column the lane computes, see
-// BExpand), then streams A row group by row group: the compiler overlaps the A reads of one
-// group with the MFMAs of the previous.
-constexpr int kV4WI = 8, kV4WJ = 4;
-
-__device__ __forceinline__ void v4_load_b(const char* st, int wc, int l16, int lg, const BExpand& bx,
-                                          u4 (&bh)[kV4WJ], u4 (&bl)[kV4WJ]) {
+// A and B fragments of one K-tile (both planes) into registers; B expanded into the real column
+// the lane computes (BExpand).
+__device__ __forceinline__ void ps_read(const char* st, int wr, int wc, int l16, int lg, int a_chunk,
+                                        const BExpand& bx, u4 (&ah)[kPsWI], u4 (&al)[kPsWI], u4 (&bh)[kPsWJ],
+                                        u4 (&bl)[kPsWJ]) {
 #pragma unroll
-  for (int j = 0; j < kV4WJ; ++j) {
+  for (int j = 0; j < kPsWJ; ++j) {
     const int row = wc + 8 * j + (l16 >> 1);
-    const char* p = st + 2 * kV3PlaneA + row * 64 + (lg ^ ((row >> 1) & 3)) * 16;
+    const char* p = st + 2 * kPsPlaneA + row * 64 + (lg ^ ((row >> 1) & 3)) * 16;
     bh[j] = *reinterpret_cast<const u4*>(p);
-    bl[j] = *reinterpret_cast<const u4*>(p + kV3PlaneB);
+    bl[j] = *reinterpret_cast<const u4*>(p + kPsPlaneB);
   }
 #pragma unroll
-  for (int j = 0; j < kV4WJ; ++j)
+  for (int i = 0; i < kPsWI; ++i) {
+    const char* p = st + (wr + 16 * i + l16) * 64 + a_chunk;
+    ah[i] = *reinterpret_cast<const u4*>(p);
+    al[i] = *reinterpret_cast<const u4*>(p + kPsPlaneA);
+  }
+#pragma unroll
+  for (int j = 0; j < kPsWJ; ++j)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       bh[j][e] = bx(bh[j][e]);
@@ -75,43 +87,46 @@ __device__ __forceinline__ void v4_load_b(const char* st, int wc, int l16, int l
     }
 }
 
-// MFMAs of every row group of one K-tile against the B fragments in registers: lo x hi, hi x lo,
-// then hi x hi, so the largest product is added last.
-__device__ __forceinline__ void v4_rows(const char* st, int wr, int l16, int a_chunk, const u4 (&bh)[kV4WJ],
-                                        const u4 (&bl)[kV4WJ], f4 (&acc)[kV4WI][kV4WJ]) {
+// The products of one K-tile for every accumulator: lo x hi, hi x lo, then hi x hi, so the
+// largest product is added last.
+__device__ __forceinline__ void ps_multiply(const u4 (&ah)[kPsWI], const u4 (&al)[kPsWI], const u4 (&bh)[kPsWJ],
+                                            const u4 (&bl)[kPsWJ], f4 (&acc)[kPsWI][kPsWJ]) {
 #pragma unroll
-  for (int i = 0; i < kV4WI; ++i) {
-    const char* p = st + (wr + 16 * i + l16) * 64 + a_chunk;
-    const bf8 ah = __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(p));
-    const bf8 al = __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(p + kV3PlaneA));
+  for (int i = 0; i < kPsWI; ++i) {
+    const bf8 a_h = __builtin_bit_cast(bf8, ah[i]);
+    const bf8 a_l = __builtin_bit_cast(bf8, al[i]);
 #pragma unroll
-    for (int j = 0; j < kV4WJ; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+    for (int j = 0; j < kPsWJ; ++j)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
 #pragma unroll
-    for (int j = 0; j < kV4WJ; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf8, bl[j]), acc[i][j], 0, 0, 0);
+    for (int j = 0; j < kPsWJ; ++j)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, __builtin_bit_cast(bf8, bl[j]), acc[i][j], 0, 0, 0);
 #pragma unroll
-    for (int j = 0; j < kV4WJ; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+    for (int j = 0; j < kPsWJ; ++j)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
   }
 }
 
-// Row tiles per raster group: after the XCD-aware reordering, the 32 workgroups that run together
-// on one XCD share 4 A panels and 8 B panels in that XCD's L2.
-constexpr int kV4GroupRows = 4;
+// Workgroup barrier that the compiler may not move any instruction across.
+__device__ __forceinline__ void ps_barrier() {
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
 
-__global__ void __launch_bounds__(kV3Threads)
-cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah, const uint32_t* __restrict__ Al,
-                  const uint32_t* __restrict__ Bh, const uint32_t* __restrict__ Bl, float2* __restrict__ C,
-                  int64_t lda, int64_t ldb, int64_t sa, int64_t sb, int64_t sc, Renorm rn) {
-  __shared__ __attribute__((aligned(1024))) char lds[kV3Stages * kV3Stage];
+__global__ void __launch_bounds__(kPsThreads)
+cgemm_pingpong_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah,
+                        const uint32_t* __restrict__ Al, const uint32_t* __restrict__ Bh,
+                        const uint32_t* __restrict__ Bl, float2* __restrict__ C, int64_t lda, int64_t ldb, int64_t sa,
+                        int64_t sb, int64_t sc, Renorm rn) {
+  __shared__ __attribute__((aligned(1024))) char lds[kPsStages * kPsStage];
 
   // workgroups are dealt round-robin to the 8 XCDs: give consecutive tiles to one XCD
-  const int64_t tiles_m = M / kV3BM, tiles_n = N / kV3BN;
+  const int64_t tiles_m = M / kPsBM, tiles_n = N / kPsBN;
   const int64_t ntiles = tiles_m * tiles_n;
   int64_t bid = blockIdx.x;
   if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
-  const int64_t group = kV4GroupRows;
+  const int64_t group = kPsGroupRows;
   const int64_t per_group = group * tiles_n;
   const int64_t gidx = bid / per_group;
   const int64_t first_m = gidx * group;
@@ -120,55 +135,85 @@ cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
   const int64_t tn = (bid % per_group) / gsize;
 
   const int64_t batch = blockIdx.z;
-  Ah += batch * sa + tm * kV3BM * lda;
-  Al += batch * sa + tm * kV3BM * lda;
-  Bh += batch * sb + tn * kV3BN * ldb;
-  Bl += batch * sb + tn * kV3BN * ldb;
+  Ah += batch * sa + tm * kPsBM * lda;
+  Al += batch * sa + tm * kPsBM * lda;
+  Bh += batch * sb + tn * kPsBN * ldb;
+  Bl += batch * sb + tn * kPsBN * ldb;
   C += batch * sc;
 
-  constexpr int WI = kV4WI, WJ = kV4WJ;
-  constexpr int NWN = kV3BN / (8 * WJ);  // 4 waves along N, 2 along M
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave / NWN) * (16 * WI);
-  const int wc = (wave % NWN) * (8 * WJ);
+  const int grp = __builtin_amdgcn_readfirstlane(wave >> 2);
+  const int wr = grp * (16 * kPsWI);
+  const int wc = (wave & 3) * (8 * kPsWJ);
   const int l16 = lane & 15, lg = lane >> 4, q = l16 & 1;
   const BExpand bx(q);
   const int a_chunk = (lg ^ ((l16 >> 1) & 3)) * 16;
 
-  f4 acc[WI][WJ];
-#pragma unroll
-  for (int i = 0; i < WI; ++i)
-#pragma unroll
-    for (int j = 0; j < WJ; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
-
-  const int64_t nk = K / kV3BK;
-  v3_issue(lds, Ah, Al, Bh, Bl, lda, ldb, 0, wave, lane);
-  if (nk > 1) v3_issue(lds + kV3Stage, Ah, Al, Bh, Bl, lda, ldb, kV3BK, wave, lane);
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
-    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    if (kt + 2 < nk)
-      v3_issue(lds + ((kt + 2) % kV3Stages) * kV3Stage, Ah, Al, Bh, Bl, lda, ldb, (kt + 2) * kV3BK, wave, lane);
-    const char* st = lds + (kt % kV3Stages) * kV3Stage;
-    u4 bh[WJ], bl[WJ];
-    v4_load_b(st, wc, l16, lg, bx, bh, bl);
-    v4_rows(st, wr, l16, a_chunk, bh, bl, acc);
+  PsLoader L;
+  {
+    const int r = lane >> 2, c = (lane & 3) ^ ((r >> 1) & 3);
+    const uint32_t pa = (uint32_t)(kPsBM * lda * 4), pb = (uint32_t)(kPsBN * ldb * 4);
+    L.ah = __builtin_amdgcn_make_buffer_rsrc((void*)Ah, (short)0, pa, 0x00020000);
+    L.al = __builtin_amdgcn_make_buffer_rsrc((void*)Al, (short)0, pa, 0x00020000);
+    L.bh = __builtin_amdgcn_make_buffer_rsrc((void*)Bh, (short)0, pb, 0x00020000);
+    L.bl = __builtin_amdgcn_make_buffer_rsrc((void*)Bl, (short)0, pb, 0x00020000);
+    L.va = (int)((r * lda + 4 * c) * 4);
+    L.vb = (int)((r * ldb + 4 * c) * 4);
+    const int w = __builtin_amdgcn_readfirstlane(wave);
+    L.ra0 = (int)(16 * w * lda * 4);
+    L.ra1 = (int)(16 * (w + 8) * lda * 4);
+    L.rb = (int)(16 * w * ldb * 4);
+    L.la0 = 16 * w * 64;
+    L.la1 = 16 * (w + 8) * 64;
+    L.lb = 2 * kPsPlaneA + 16 * w * 64;
   }
+
+  f4 acc[kPsWI][kPsWJ];
+#pragma unroll
+  for (int i = 0; i < kPsWI; ++i)
+#pragma unroll
+    for (int j = 0; j < kPsWJ; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+  u4 ah[kPsWI], al[kPsWI], bh[kPsWJ], bl[kPsWJ];
+
+  const int nk = (int)(K / kPsBK);
+  ps_issue(L, lds, 0);
+  if (nk > 1) ps_issue(L, lds + kPsStage, kPsBK * 4);
+  if (nk > 1) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+  else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  ps_barrier();
+  // Barriers seen by group 0: [read t | multiply t] for every t, then one more; by group 1: one
+  // first, then [read t | multiply t]: both groups pass the same number of barriers.  Tile t + 2
+  // goes into the stage of tile t - 1, which both groups finished reading before the barrier that
+  // precedes this read half; each wave's loads of tile t + 1 are complete before the barrier that
+  // ends this read half (only the batch just issued stays in flight).
+  if (grp == 1) ps_barrier();
+  int s_cur = 0;  // stage of tile t
+  for (int t = 0; t < nk; ++t) {
+    const int s_t2 = s_cur == 0 ? kPsStages - 1 : s_cur - 1;  // stage of tile t + 2
+    if (t + 2 < nk) ps_issue(L, lds + s_t2 * kPsStage, (t + 2) * kPsBK * 4);
+    ps_read(lds + s_cur * kPsStage, wr, wc, l16, lg, a_chunk, bx, ah, al, bh, bl);
+    if (t + 2 < nk) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    ps_barrier();
+    ps_multiply(ah, al, bh, bl, acc);
+    ps_barrier();
+    s_cur = s_cur == kPsStages - 1 ? 0 : s_cur + 1;
+  }
+  if (grp == 0) ps_barrier();
 
   // renormalisation is read only now, so that nothing else is in flight during the load ring
   float scale_a, scale_b, unscale;
   renorm_begin<P_BF16X3>(rn, nullptr, nullptr, scale_a, scale_b, unscale);
   float mx = 0.f;
 #pragma unroll
-  for (int i = 0; i < WI; ++i)
+  for (int i = 0; i < kPsWI; ++i)
 #pragma unroll
-    for (int j = 0; j < WJ; ++j) {
+    for (int j = 0; j < kPsWJ; ++j) {
       const f4 v = acc[i][j] * unscale;
       const float s0 = q ? v[0] : v[2], s1 = q ? v[1] : v[3];
       const float r0 = __shfl_xor(s0, 1), r1 = __shfl_xor(s1, 1);
-      const int64_t row = tm * kV3BM + wr + 16 * i + 4 * lg + (q ? 2 : 0);
-      const int64_t col = tn * kV3BN + wc + 8 * j + (l16 >> 1);
+      const int64_t row = tm * kPsBM + wr + 16 * i + 4 * lg + (q ? 2 : 0);
+      const int64_t col = tn * kPsBN + wc + 8 * j + (l16 >> 1);
       float2 o0, o1;
       if (q) { o0 = make_float2(r0, v[2]); o1 = make_float2(r1, v[3]); }
       else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
@@ -181,7 +226,7 @@ cgemm_v4_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ 
 
 bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K) {
   auto p2 = [](int64_t x) { return x > 0 && (x & (x - 1)) == 0; };
-  return p2(M) && p2(N) && p2(K) && M >= kV3BM && N >= kV3BN && K >= kV3BK;
+  return p2(M) && p2(N) && p2(K) && M >= kPsBM && N >= kPsBN && K >= kPsBK && K + 64 <= kPsMaxLd;
 }
 
 // A, B: split operands, each a hi plane followed by a lo plane (rows x K bfloat16 pairs each,
@@ -193,7 +238,7 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
   if (!cgemm_presplit_fits(M, N, K)) return hipErrorInvalidValue;
   if (lda == 0) lda = K;
   if (ldb == 0) ldb = K;
-  if (lda < K || ldb < K || (lda & 3) || (ldb & 3)) return hipErrorInvalidValue;
+  if (lda < K || ldb < K || (lda & 3) || (ldb & 3) || lda > kPsMaxLd || ldb > kPsMaxLd) return hipErrorInvalidValue;
   if (rn.c) {
     const hipError_t e = launch_renorm_reset(st, rn.c);
     if (e != hipSuccess) return e;
@@ -202,10 +247,10 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
   const uint32_t* b = reinterpret_cast<const uint32_t*>(B);
   const uint32_t* al = a + M * lda;
   const uint32_t* bl = b + N * ldb;
-  const int64_t tiles = (M / kV3BM) * (N / kV3BN);
+  const int64_t tiles = (M / kPsBM) * (N / kPsBN);
   const dim3 grid((unsigned)tiles, 1, (unsigned)batch);
-  hipLaunchKernelGGL(cgemm_v4_presplit, grid, dim3(kV3Threads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb, 2 * sa,
-                     2 * sb, sc, rn);
+  hipLaunchKernelGGL(cgemm_pingpong_presplit, grid, dim3(kPsThreads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb,
+                     2 * sa, 2 * sb, sc, rn);
   return hipGetLastError();
 }
 

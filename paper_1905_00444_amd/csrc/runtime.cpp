@@ -1507,11 +1507,11 @@ qf_status qf_cgemm_presplit(qf_ctx* c, int64_t M, int64_t N, int64_t K, const vo
                             int64_t lda, int64_t ldb) {
   if (!c || !A || !B || !C) return fail(c, QF_ERR_ARG, "qf_cgemm_presplit: null pointer");
   if (!cgemm_presplit_fits(M, N, K))
-    return fail(c, QF_ERR_UNSUPPORTED, "qf_cgemm_presplit needs powers of two with M >= 256, N >= 128, K >= 16");
+    return fail(c, QF_ERR_UNSUPPORTED, "qf_cgemm_presplit needs powers of two with M >= 256, N >= 128, 16 <= K <= 2^20");
   if (lda == 0) lda = K;
   if (ldb == 0) ldb = K;
-  if (lda < K || ldb < K || (lda & 3) || (ldb & 3))
-    return fail(c, QF_ERR_ARG, "qf_cgemm_presplit: row pitches must be >= K and multiples of 4 words");
+  if (lda < K || ldb < K || (lda & 3) || (ldb & 3) || lda > ((int64_t)1 << 21) || ldb > ((int64_t)1 << 21))
+    return fail(c, QF_ERR_ARG, "qf_cgemm_presplit: row pitches must be >= K, <= 2^21 and multiples of 4 words");
   QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, reinterpret_cast<float2*>(C), 1, M * lda, N * ldb, M * N,
                                   Renorm{}, lda, ldb));
   return QF_OK;
