@@ -224,6 +224,21 @@ qf_status qf_amplitudes(qf_plan* plan, int n_batch, const uint8_t* bits_dev, int
 qf_status qf_backward(qf_plan* plan, int n_batch, const uint8_t* bits_dev, const double* cot_dev,
                       int64_t s_begin, int64_t s_end, float* grad_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): qf_amplitudes with every tensor of the plan in a
+ * library-owned device array of qf_static_scratch_bytes() = 64 MiB per device (a file-scope
+ * __device__ array, loaded with the library and held until the process ends) instead of the
+ * context's workspace, which it neither needs nor touches.  Same arguments, ordering and result
+ * (out_dev += amplitudes) as qf_amplitudes.  It allocates nothing (no hipMalloc / hipFree, no
+ * graph, no events).  Every call on one device shares that device's array, and the array keeps
+ * the last call's contents: calls that overlap on one device (several streams, contexts or host
+ * threads) race and must be serialised by the caller.  Errors: QF_ERR_WORKSPACE when the plan's
+ * workspace_bytes exceeds the array, QF_ERR_UNSUPPORTED for plans created with QF_PLAN_GRAPH, and
+ * those of qf_amplitudes. */
+qf_status qf_amplitudes_static(qf_plan* plan, int n_batch, const uint8_t* bits_dev, int64_t s_begin,
+                               int64_t s_end, double* out_dev);
+qf_status qf_static_scratch_bytes(size_t* bytes);
+
 /* --- kernel-level entry points (the steps of one contraction; used by tests and bench) --- */
 
 /* Permute ("T" of TTGT, Sec. III-E): dst[j] = scale * src[src_base + sum_i bit_i(j) * 2^perm[i]]

@@ -65,6 +65,8 @@ EXPORTS = {
     "qf_circuit_set_values": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
     "qf_circuit_destroy": (None, [C.c_void_p]),
     "qf_plan_step_info": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(qf_step_info)]),
+    "qf_amplitudes_static": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]),
+    "qf_static_scratch_bytes": (C.c_int, [C.POINTER(C.c_size_t)]),
     "qf_plan_graph_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "qf_plan_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(qf_plan_desc), C.POINTER(C.c_void_p)]),
     "qf_plan_info_get": (C.c_int, [C.c_void_p, C.POINTER(qf_plan_info)]),

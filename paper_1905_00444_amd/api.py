@@ -225,6 +225,26 @@ class Plan:
         check(st, self.ctx.h)
         return out
 
+    def amplitudes_static(self, bits, s_begin: int = 0, s_end: Optional[int] = None, out=None):
+        """As amplitudes(), through qf_amplitudes_static: the plan runs in the library's own
+        64 MiB device array instead of the context's workspace (no allocation by the library;
+        `bits` and `out` must already be device tensors when the caller cannot allocate)."""
+        torch = _torch()
+        if s_end is None:
+            s_end = self.info()["n_slices"]
+        with torch.cuda.stream(self.ctx.stream):
+            if isinstance(bits, np.ndarray):
+                bits = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint8)).to(self.ctx.device)
+            nb = bits.shape[0]
+            if out is None:
+                out = torch.zeros((nb, 2 ** self.n_open), dtype=torch.complex128, device=self.ctx.device)
+            assert bits.dtype == torch.uint8 and bits.is_contiguous() and out.dtype == torch.complex128
+            st = self.ctx.lib.qf_amplitudes_static(self.h, nb, C.c_void_p(bits.data_ptr()), int(s_begin), int(s_end),
+                                                   C.c_void_p(out.data_ptr()))
+        self._bits_keepalive = bits
+        check(st, self.ctx.h)
+        return out
+
     def backward(self, bits, cot, s_begin: int = 0, s_end: Optional[int] = None, grad=None):
         """Gradient (n_ops, 4) complex64 of the amplitudes contracted with the cotangent `cot`
         (n_batch, 2^n_open complex128): grad_G = sum_b cot_b conj(d a_b / d G), added into `grad`."""

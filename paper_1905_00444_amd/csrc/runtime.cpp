@@ -22,6 +22,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -1223,6 +1224,71 @@ extern "C" qf_status qf_amplitudes(qf_plan* p, int n_batch, const uint8_t* bits_
     }
   }
   return QF_OK;
+}
+
+// ---- qf_amplitudes on a library-owned scratch array (no allocation) ----------------------------
+// Every tensor of a plan lives in one workspace; this entry point runs a plan on a file-scope device
+// array instead of the context's workspace, for callers that cannot allocate device memory.  Each
+// device holds its own copy of the array (loaded with the library's code object, held until the
+// process ends); its address on a device comes from hipGetSymbolAddress, taken once per device
+// with that device current.
+static constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char qf_static_scratch[kStaticScratchBytes];
+static constexpr int kMaxStaticDevices = 64;
+static std::mutex g_static_mu;
+static char* g_static_ptr[kMaxStaticDevices] = {};
+
+static qf_status static_scratch_ptr(qf_ctx* c, char** out) {
+  if (c->device < 0 || c->device >= kMaxStaticDevices) return fail(c, QF_ERR_UNSUPPORTED, "device id beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[c->device]) {
+    int prev = 0;
+    QF_HIP(c, hipGetDevice(&prev));
+    QF_HIP(c, hipSetDevice(c->device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(qf_static_scratch));
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(qf_static_scratch)");
+    if (!ptr) return fail(c, QF_ERR_HIP, "hipGetSymbolAddress(qf_static_scratch) returned null");
+    g_static_ptr[c->device] = reinterpret_cast<char*>(ptr);
+  }
+  *out = g_static_ptr[c->device];
+  return QF_OK;
+}
+
+extern "C" qf_status qf_static_scratch_bytes(size_t* bytes) {
+  if (!bytes) return QF_ERR_ARG;
+  *bytes = kStaticScratchBytes;
+  return QF_OK;
+}
+
+extern "C" qf_status qf_amplitudes_static(qf_plan* p, int n_batch, const uint8_t* bits_dev, int64_t s_begin,
+                                          int64_t s_end, double* out_dev) {
+  if (!p || !p->ctx || !p->circ) return QF_ERR_ARG;
+  qf_ctx* c = p->ctx;
+  if (p->graph) return fail(c, QF_ERR_UNSUPPORTED, "qf_amplitudes_static: graph-captured plans allocate their graph");
+  if (p->arena_end > kStaticScratchBytes)
+    return fail(c, QF_ERR_WORKSPACE, "qf_amplitudes_static: the plan needs " + std::to_string(p->arena_end) +
+                                         " bytes, the static scratch holds " + std::to_string(kStaticScratchBytes));
+  char* ptr = nullptr;
+  qf_status st = static_scratch_ptr(c, &ptr);
+  if (st != QF_OK) return st;
+  // run on the static array: the world-lines are rebuilt in it (every region that must start at a
+  // known value, the chain counter, the scale table and the max-magnitude slots, is written by
+  // the call itself before it is read), profiling (which may create events) is off
+  char* ws = c->ws;
+  const size_t ws_bytes = c->ws_bytes;
+  const bool prof = c->profile;
+  c->ws = ptr;
+  c->ws_bytes = kStaticScratchBytes;
+  c->profile = false;
+  c->last_built = nullptr;
+  st = qf_amplitudes(p, n_batch, bits_dev, s_begin, s_end, out_dev);
+  c->ws = ws;
+  c->ws_bytes = ws_bytes;
+  c->profile = prof;
+  c->last_built = nullptr;  // the caller's workspace is rebuilt on its next use
+  return st;
 }
 
 // dst = [Y bits | X bits] from src = [X bits | Y bits] (X most significant in src)
