@@ -34,7 +34,8 @@ def parse():
     ap.add_argument("--whole-prefixes", type=int, default=1,
                     help="prefixes whose whole path sum (every contributing slice) is timed in split-BF16")
     ap.add_argument("--c5-slices", type=int, default=256,
-                    help="8x9-d24: slices per bitstring of the hand plan's 256 (a multiple of 16 or all)")
+                    help="8x9-d24: slices per bitstring of the hand plan's 256")
+    ap.add_argument("--c5-batch", type=int, default=256, help="8x9-d24: chains per launch group (a power of two)")
     ap.add_argument("--cpu-reps", type=int, default=10, help="prefixes in the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-subcheck", action="store_true")
@@ -52,11 +53,12 @@ def parse():
 
 def bench_8x9(args):
     """70 qubits (8x9 minus two corners, 1+24+1, bond 8): 16 bitstrings x all 256 slices (or the
-    first --c5-slices) of the two-halves plan as 4096 chains, 16 per launch, replayed from one
-    captured hipGraph; and the
-    whole amplitudes of the same 16 bitstrings with the plan the search finds (no cut at 2^27)."""
+    first --c5-slices) of the two-halves plan as 4096 chains in launch groups of --c5-batch slices
+    of one bitstring (the steps that no cut touches run once per group), one captured hipGraph per
+    call; and the whole amplitudes of the same 16 bitstrings with the plan the search finds (no
+    cut at 2^27)."""
     import torch
-    from paper_1905_00444_amd import Context, Circuit, Plan, planner
+    from paper_1905_00444_amd import Context, Circuit, Plan, planner, autotune
     from workloads.bitstrings import random_bitstrings
     from workloads.circuits import generate
     from workloads.plans import plan_8x9, C5_REMOVED
@@ -68,8 +70,14 @@ def bench_8x9(args):
     cobj = Circuit(ctx, text)
     rec = {"metric": "70-qubit (8x9 - 2, 1+24+1) amplitudes", "n_gpus": 1, "data": "synthetic, seeded",
            "dtype": "bf16x3 (FP32 accumulate)"}
-    G, S = 16, max(1, min(256, args.c5_slices))
+    G, S = args.c5_batch, max(1, min(256, args.c5_slices))
     p = Plan(ctx, cobj, hand, "bf16x3", batch=G, graph=True)
+    ctx.ensure_workspace(p.info()["workspace_bytes"])
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        autotune(p)
+        ctx.synchronize()
+        print(f"bench: 8x9 autotune {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     with torch.cuda.stream(ctx.stream):
         bits_t = torch.from_numpy(bits).to(ctx.device)  # one device copy: the captured graph keys on it
     out = p.amplitudes(bits_t, 0, S)  # captures the graph, warms up
@@ -82,13 +90,18 @@ def bench_8x9(args):
     p.amplitudes(bits_t, 0, S, out=out)
     ctx.synchronize()
     dt = time.perf_counter() - t0
+    launches, nodes = p.graph_info()
     chains = 16 * S
-    fl = chains * p.info()["flops_per_slice"]
-    rec["batched_graph"] = {"chains": chains, "chains_per_launch": G, "slices": S, "seconds": dt,
-                            "chains_per_s": chains / dt, "complex_tflops": fl / dt / 1e12,
-                            "plan": "two halves, cuts (0,4)-(0,5) 3 bits, (1,4)-(1,5) 3 bits, (2,4)-(2,5) 2 bits"}
+    fl = 16 * p.flops(0, S)  # executed: cut-independent steps once per launch group
+    rec["batched_graph"] = {"chains": chains, "chains_per_launch_group": G, "slices": S, "seconds": dt,
+                            "amplitudes_per_s": 16 / dt if S == 256 else None,
+                            "chains_per_s": chains / dt, "complex_tflops": fl / dt / 1e12, "flops_executed": fl,
+                            "flops_without_reuse": chains * p.info()["flops_per_slice"],
+                            "graph_launches_per_call": 1, "graph_nodes": nodes,
+                            "plan": "two halves, cuts (0,4)-(0,5) 3 bits, (1,4)-(1,5) 3 bits, (2,4)-(2,5) 2 bits; "
+                                    "the cells carrying the cuts absorbed last as two 3-cell strips"}
     hand_amps = out.cpu().numpy()
-    print(f"bench: 8x9 timed pass {dt:.1f} s", file=sys.stderr, flush=True)
+    print(f"bench: 8x9 timed pass {dt:.2f} s", file=sys.stderr, flush=True)
     del p
     best = planner.search(text, 27)
     q = Plan(ctx, cobj, best.plan, "bf16x3")

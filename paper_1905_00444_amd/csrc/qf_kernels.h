@@ -103,12 +103,14 @@ struct LeafDesc {
   int32_t pos[kMaxLeafCut];      // bit position in the world-line
 };
 
-// For chains c = *chain0 + g (g < G): b = c / s_range, s = s_begin + c % s_range;
-// base_table[g * n_leaves + l] = world-line offset of leaf l's fixed bits; chain_b[g] = b
-// (-1 past n_chains).
+// Chain g (g < G) of the launch group that *chain0 names.  gpb == 0: chains c = *chain0 + g in
+// bitstring-major order, b = c / s_range, s = s_begin + c % s_range, idle past n_chains.  gpb > 0
+// (groups per bitstring): group q = *chain0 / G holds slices s_begin + (q mod gpb) G + g of
+// bitstring b = q / gpb, idle past s_begin + s_range.  base_table[g * n_leaves + l] = world-line
+// offset of leaf l's fixed bits; chain_b[g] = b (-1 for an idle chain).
 hipError_t launch_chain_setup(hipStream_t st, const int64_t* chain0, int G, int n_leaves, const LeafDesc* leaves,
                               const uint8_t* bits, int n_qubits, int64_t s_begin, int64_t s_range, int64_t n_chains,
-                              int64_t* base_table, int32_t* chain_b);
+                              int64_t gpb, int64_t* base_table, int32_t* chain_b);
 // out[chain_b[g]][j] += root[g][sum_t bit_t(j) << pos[t]] for g = 0..G-1 in order (FP64).
 hipError_t launch_slice_accumulate_batched(hipStream_t st, const float2* root, int k, const int* pos, int G,
                                            const int32_t* chain_b, double2* out,

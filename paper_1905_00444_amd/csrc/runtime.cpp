@@ -110,9 +110,11 @@ static size_t operand_elems(const Operand& op) {
 
 struct Step {
   int l = -1, r = -1;
-  Operand A, B;           // roles after the swap (A has the larger free volume)
+  Operand A, B;           // roles after the swap (A has the larger free volume, except that in
+                          // plans with group hoisting a cut-independent operand is B)
   int m_bits = 0, n_bits = 0, k_bits = 0;
   bool presplit = false;  // split-BF16 GEMM on operands split by their permutes
+  bool fold = false;      // group hoisting, B shared by the group's chains: one GEMM of G M rows
   double flops = 0.0;
   size_t out = 0;         // arena offset of the result
 };
@@ -158,6 +160,11 @@ struct qf_plan {
   // batched plans: G chains per launch
   int G = 1;
   bool graph = false;
+  // batched forward plans with cuts: the chains of one launch group share one bitstring (groups
+  // never straddle bitstrings), and every step whose result depends on no cut (step_inv) runs
+  // once per group with batch 1; later steps read its result with batch stride 0
+  bool ghoist = false;
+  std::vector<char> step_inv;
   std::vector<LeafDesc> leaf_desc;
   size_t off_leafdesc = 0, off_btable = 0, off_chainb = 0;
   hipGraphExec_t gexec = nullptr;
@@ -322,6 +329,14 @@ static bool is_identity(const std::vector<int>& perm) {
     if (perm[i] != (int)i) return false;
   return true;
 }
+
+// Chains per launch of step i and of one of its operands: G, or 1 for what a launch group
+// computes once (batched plans with group hoisting, results that depend on no cut).
+static int step_batch(const qf_plan* p, size_t i) { return (p->ghoist && p->step_inv[i]) ? 1 : p->G; }
+static bool operand_invariant(const qf_plan* p, const Operand& op) {
+  return p->ghoist && p->nodes[op.node].dep_cuts == 0;
+}
+static int operand_batch(const qf_plan* p, const Operand& op) { return operand_invariant(p, op) ? 1 : p->G; }
 
 qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, qf_plan** out) {
   if (!ctx || !circ || !d || !out) return fail(ctx, QF_ERR_ARG, "qf_plan_create: null argument");
@@ -529,6 +544,10 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   }
 
   // ---- TTGT roles and layouts
+  // batched forward plans with cuts run the cut-independent steps once per launch group (group
+  // hoisting, below); a step that combines such a shared operand with a per-chain one takes the
+  // shared one as B, so that the group's chains stack along M in one GEMM
+  const bool group_hoist = p->G > 1 && !p->backward && !(d->flags & QF_PLAN_NO_HOIST) && p->total_cut_bits > 0;
   p->flops_per_slice = p->flops_hoisted = p->permute_bytes = p->max_step_flops = 0.0;
   for (int i = 0; i < (int)p->steps.size(); ++i) {
     Step& st = p->steps[i];
@@ -539,6 +558,7 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     for (int lab : X->labels) if (contains(Y->labels, lab)) K.push_back(lab);
     int xf = (int)X->labels.size() - (int)K.size(), yf = (int)Y->labels.size() - (int)K.size();
     if (yf > xf) { std::swap(X, Y); std::swap(xid, yid); std::swap(xf, yf); }
+    if (group_hoist && X->dep_cuts == 0 && Y->dep_cuts != 0) { std::swap(X, Y); std::swap(xid, yid); std::swap(xf, yf); }
     // K order: keep an intermediate operand in place when its contracted bits already trail
     auto trailing = [&](const Node* nd) {
       if (nd->leaf) return false;
@@ -606,6 +626,22 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     p->gscratch_bytes = need;
   }
 
+  // ---- batched plans with cuts: steps that depend on no cut run once per launch group
+  if (group_hoist) {
+    p->step_inv.assign(p->steps.size(), 0);
+    for (size_t i = 0; i < p->steps.size(); ++i)
+      if (p->nodes[n + i].dep_cuts == 0) {
+        p->step_inv[i] = 1;
+        p->ghoist = true;
+      }
+    if (!p->ghoist) p->step_inv.clear();
+    for (size_t i = 0; p->ghoist && i < p->steps.size(); ++i) {
+      Step& st = p->steps[i];
+      st.fold = !p->step_inv[i] && !st.presplit && operand_invariant(p.get(), st.B) &&
+                !operand_invariant(p.get(), st.A);
+    }
+  }
+
   // ---- arena
   size_t cur = kCtxScratch;
   p->off_gates = cur;
@@ -620,9 +656,10 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   const int S = (int)p->steps.size();
   for (int i = 0; i < S; ++i) {
     Node& nd = p->nodes[n + i];
-    const size_t G = (size_t)p->G;
+    const size_t G = (size_t)step_batch(p.get(), i);
     const size_t bytes = align_up(G * (sizeof(float2) << nd.labels.size()));
     Step& st = p->steps[i];
+    const size_t GA = (size_t)operand_batch(p.get(), st.A), GB = (size_t)operand_batch(p.get(), st.B);
     if (p->backward) {
       // every forward tensor is kept for the reverse sweep, next to its environment
       pers.push_back({bytes, 0, S, &nd.offset});
@@ -633,8 +670,8 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     }
     if (nd.persistent) pers.push_back({bytes, 0, S, &nd.offset});
     else trans.push_back({bytes, i, (i == S - 1) ? S : nd.consumer, &nd.offset});
-    if (st.A.permute) trans.push_back({align_up(G * sizeof(float2) * operand_elems(st.A)), i, i, &st.A.buf});
-    if (st.B.permute) trans.push_back({align_up(G * sizeof(float2) * operand_elems(st.B)), i, i, &st.B.buf});
+    if (st.A.permute) trans.push_back({align_up(GA * sizeof(float2) * operand_elems(st.A)), i, i, &st.A.buf});
+    if (st.B.permute) trans.push_back({align_up(GB * sizeof(float2) * operand_elems(st.B)), i, i, &st.B.buf});
   }
   if (p->renorm) pers.push_back({align_up((n + S) * sizeof(NodeScale)), 0, S, &p->off_scales});
   if (p->gscratch_bytes) pers.push_back({align_up(p->gscratch_bytes), 0, S, &p->off_gscratch});
@@ -725,6 +762,13 @@ void qf_plan_destroy(qf_plan* plan) {
 static double schedule_flops(const qf_plan* p, int64_t s0, int64_t s1, bool first_bitstring) {
   double total = 0.0;
   const int n = p->n;
+  if (p->ghoist) {
+    // every launch group of G slices runs the cut-independent steps once, the others per slice
+    const int64_t groups = (s1 - s0 + p->G - 1) / p->G;
+    for (size_t i = 0; i < p->steps.size(); ++i)
+      total += p->steps[i].flops * (double)(p->step_inv[i] ? groups : (s1 - s0));
+    return total;
+  }
   for (int64_t s = s0; s < s1; ++s) {
     for (size_t i = 0; i < p->steps.size(); ++i) {
       const Node& nd = p->nodes[n + i];
@@ -925,13 +969,15 @@ static const NodeScale* root_scale(qf_plan* p) {
 // One GEMM of the plan's precision (FP16 without renormalisation takes the operands' max
 // magnitudes first).
 static qf_status plan_gemm(qf_plan* p, int64_t M, int64_t N, int64_t K, const float2* A, const float2* B, float2* C,
-                           int64_t batch = 1, const Renorm& rn = Renorm{}) {
+                           int64_t batch = 1, const Renorm& rn = Renorm{}, int64_t sa = -1, int64_t sb = -1) {
   qf_ctx* c = p->ctx;
+  if (sa < 0) sa = M * K;  // batch strides: dense per chain, or 0 for an operand shared by the batch
+  if (sb < 0) sb = N * K;
   const uint32_t *amA = nullptr, *amB = nullptr;
   if (p->precision == QF_FP16 && !rn.c) {
     uint32_t* slots = reinterpret_cast<uint32_t*>(c->ws);  // context scratch: 2 slots
-    QF_HIP(c, launch_amax(c->stream, A, batch * M * K, slots));
-    QF_HIP(c, launch_amax(c->stream, B, batch * N * K, slots + 1));
+    QF_HIP(c, launch_amax(c->stream, A, (sa ? batch : 1) * M * K, slots));
+    QF_HIP(c, launch_amax(c->stream, B, (sb ? batch : 1) * N * K, slots + 1));
     amA = slots;
     amB = slots + 1;
   }
@@ -941,7 +987,7 @@ static qf_status plan_gemm(qf_plan* p, int64_t M, int64_t N, int64_t K, const fl
     if (it != c->tune.end()) variant = it->second;
   }
   float2* scratch = p->gscratch_bytes ? wsp(c, p->off_gscratch) : nullptr;
-  QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, batch, M * K, N * K, M * N, amA, amB, rn,
+  QF_HIP(c, launch_cgemm_ex(c->stream, p->precision, M, N, K, A, B, C, batch, sa, sb, M * N, amA, amB, rn,
                             variant, scratch, p->gscratch_bytes));
   return QF_OK;
 }
@@ -1042,7 +1088,7 @@ static qf_status run_operand_batched(qf_plan* p, const Operand& op, const float2
   a.nbits = op.nbits;
   for (int i = 0; i < op.nbits; ++i) a.perm[i] = op.perm[i];
   a.scale = 1.0f;
-  a.batch = p->G;
+  a.batch = operand_batch(p, op);  // 1: the launch group's chains share this operand
   a.dst_bstride = (int64_t)operand_elems(op);
   const float2* src;
   if (nd.leaf) {
@@ -1069,11 +1115,13 @@ static qf_status enqueue_group(qf_plan* p, const uint8_t* bits_dev, int64_t s_be
   const int n = p->n, G = p->G, k = (int)p->open.size();
   int64_t* chain0 = reinterpret_cast<int64_t*>(c->ws + 8);
   int32_t* chain_b = reinterpret_cast<int32_t*>(c->ws + p->off_chainb);
+  const int64_t gpb = p->ghoist ? (s_range + G - 1) / G : 0;  // launch groups per bitstring
   QF_HIP(c, launch_chain_setup(c->stream, chain0, G, n, reinterpret_cast<const LeafDesc*>(c->ws + p->off_leafdesc),
-                               bits_dev, n, s_begin, s_range, n_chains,
+                               bits_dev, n, s_begin, s_range, n_chains, gpb,
                                reinterpret_cast<int64_t*>(c->ws + p->off_btable), chain_b));
   for (size_t i = 0; i < p->steps.size(); ++i) {
     const Step& st = p->steps[i];
+    const int Gi = step_batch(p, i);
     const float2 *A, *B;
     qf_status e = run_operand_batched(p, st.A, &A);
     if (e != QF_OK) return e;
@@ -1081,6 +1129,7 @@ static qf_status enqueue_group(qf_plan* p, const uint8_t* bits_dev, int64_t s_be
     if (e != QF_OK) return e;
     float2* C = wsp(c, p->nodes[n + i].offset);
     const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+    const bool shared_a = operand_invariant(p, st.A), shared_b = operand_invariant(p, st.B);
     const bool timed = timed_ok && c->profile && st.flops == p->max_step_flops;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
@@ -1091,15 +1140,19 @@ static qf_status enqueue_group(qf_plan* p, const uint8_t* bits_dev, int64_t s_be
     const Renorm rn = step_renorm(p, i);
     if (st.presplit) {
       const int64_t lda = split_ld(st.A), ldb = split_ld(st.B);
-      QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, G, M * lda, N * ldb, M * N, rn, lda, ldb));
+      QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, Gi, shared_a ? 0 : M * lda, shared_b ? 0 : N * ldb,
+                                      M * N, rn, lda, ldb));
     } else {
-      e = plan_gemm(p, M, N, K, A, B, C, G, rn);
+      // folded: the group's per-chain A matrices are consecutive, so with B shared they form one
+      // A of G M rows and the product's rows are the chains' results in order
+      e = st.fold ? plan_gemm(p, Gi * M, N, K, A, B, C, 1, rn)
+                  : plan_gemm(p, M, N, K, A, B, C, Gi, rn, shared_a ? 0 : M * K, shared_b ? 0 : N * K);
       if (e != QF_OK) return e;
     }
     if (timed && e0 && e1) {
       QF_HIP(c, hipEventRecord(e1, c->stream));
       c->ev_used.push_back({e0, e1});
-      c->prof_flops += st.flops * G;
+      c->prof_flops += st.flops * Gi;
       ++c->prof_launches;
     }
   }
@@ -1116,7 +1169,9 @@ static qf_status enqueue_call(qf_plan* p, int n_batch, const uint8_t* bits_dev, 
   qf_ctx* c = p->ctx;
   const int64_t s_range = s_end - s_begin;
   const int64_t n_chains = (int64_t)n_batch * s_range;
-  const int64_t groups = (n_chains + p->G - 1) / p->G;
+  // group hoisting: each bitstring's slices in groups of G (the last one of a bitstring may be
+  // partly idle); otherwise consecutive chains, bitstring-major, G per group
+  const int64_t groups = p->ghoist ? n_batch * ((s_range + p->G - 1) / p->G) : (n_chains + p->G - 1) / p->G;
   QF_HIP(c, launch_chain_counter(c->stream, reinterpret_cast<int64_t*>(c->ws + 8), 0, 0));
   for (int64_t g = 0; g < groups; ++g) {
     qf_status e = enqueue_group(p, bits_dev, s_begin, s_range, n_chains, out_dev, timed_ok);
@@ -1369,7 +1424,7 @@ static qf_status backward_group(qf_plan* p, const uint8_t* bits_dev, const doubl
   int64_t* chain0 = reinterpret_cast<int64_t*>(c->ws + 8);
   int32_t* chain_b = reinterpret_cast<int32_t*>(c->ws + p->off_chainb);
   QF_HIP(c, launch_chain_setup(c->stream, chain0, G, n, reinterpret_cast<const LeafDesc*>(c->ws + p->off_leafdesc),
-                               bits_dev, n, s_begin, s_range, n_chains,
+                               bits_dev, n, s_begin, s_range, n_chains, 0,
                                reinterpret_cast<int64_t*>(c->ws + p->off_btable), chain_b));
   // forward, every tensor of every chain kept
   for (size_t i = 0; i < p->steps.size(); ++i) {
@@ -1747,14 +1802,15 @@ static std::string read_tune_file(const char* path, std::map<std::array<int64_t,
 // Average milliseconds of one GEMM launch of the given variant (a first launch warms up and is
 // used to size the repetitions: about 10 ms of work, 2 to 20 launches).  *ms < 0: not timed.
 static qf_status time_variant(qf_ctx* c, const qf_plan* p, int variant, int64_t M, int64_t N, int64_t K,
-                              int64_t G, const float2* A, const float2* B, float2* C, float give_up_ms, float* ms) {
+                              int64_t G, const float2* A, const float2* B, float2* C, float give_up_ms, float* ms,
+                              int64_t sa, int64_t sb) {
   const int prec = p->precision;
   float2* scratch = p->gscratch_bytes ? reinterpret_cast<float2*>(c->ws + p->off_gscratch) : nullptr;
   hipEvent_t e0 = take_event(c), e1 = take_event(c);
   if (!e0 || !e1) return fail(c, QF_ERR_HIP, "hipEventCreate failed");
   auto launch = [&]() {
-    return launch_cgemm_ex(c->stream, prec, M, N, K, A, B, C, G, M * K, N * K, M * N, nullptr, nullptr, Renorm{},
-                           variant, scratch, p->gscratch_bytes);
+    return launch_cgemm_ex(c->stream, prec, M, N, K, A, B, C, G, sa, sb, M * N, nullptr, nullptr, Renorm{}, variant,
+                           scratch, p->gscratch_bytes);
   };
   *ms = -1.f;
   QF_HIP(c, hipEventRecord(e0, c->stream));
@@ -1814,12 +1870,14 @@ extern "C" qf_status qf_autotune(qf_ctx* c, const qf_plan* pc, const char* path)
   }
   std::map<std::array<int64_t, 5>, std::string>& measured = c->tune_times;
   const int n = p->n;
-  const int64_t G = p->G;
   uint32_t seed = 1;
   for (size_t i = 0; i < p->steps.size(); ++i) {
     const Step& st = p->steps[i];
     if (st.presplit) continue;
-    const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
+    const int64_t GA = operand_batch(p, st.A), GB = operand_batch(p, st.B);
+    const int64_t G = st.fold ? 1 : step_batch(p, i);  // chains of this step's launches
+    const int64_t M = ((int64_t)1 << st.m_bits) * (st.fold ? GA : 1), N = (int64_t)1 << st.n_bits,
+                  K = (int64_t)1 << st.k_bits;
     const std::array<int64_t, 5> key = {(int64_t)p->precision, M, N, K, G};
     auto fit = file.find(key);
     if (fit != file.end()) {
@@ -1833,14 +1891,15 @@ extern "C" qf_status qf_autotune(qf_ctx* c, const qf_plan* pc, const char* path)
     float2* A = wsp(c, st.A.permute ? st.A.buf : na.offset);
     float2* B = wsp(c, st.B.permute ? st.B.buf : nb.offset);
     float2* C = wsp(c, p->nodes[n + i].offset);
-    QF_HIP(c, launch_fill_random(c->stream, A, G * M * K, seed++));
-    QF_HIP(c, launch_fill_random(c->stream, B, G * N * K, seed++));
+    QF_HIP(c, launch_fill_random(c->stream, A, (st.fold ? 1 : GA) * M * K, seed++));
+    QF_HIP(c, launch_fill_random(c->stream, B, GB * N * K, seed++));
+    const int64_t sa = (GA > 1 && !st.fold) ? M * K : 0, sb = GB > 1 ? N * K : 0;
     int best = GEMM_AUTO;
     float best_ms = 0.f;
     std::string times = "{";
     for (int v : tune_candidates(p->precision, M, N, K, G)) {
       float ms = 0.f;
-      qf_status e = time_variant(c, p, v, M, N, K, G, A, B, C, best > 0 ? 3.f * best_ms : 0.f, &ms);
+      qf_status e = time_variant(c, p, v, M, N, K, G, A, B, C, best > 0 ? 3.f * best_ms : 0.f, &ms, sa, sb);
       if (e != QF_OK) return e;
       char buf[64];
       std::snprintf(buf, sizeof buf, "%s\"%s\": %.2f", times.size() > 1 ? ", " : "", kVariantName[v], 1e3 * ms);

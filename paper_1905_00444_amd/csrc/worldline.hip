@@ -302,16 +302,26 @@ hipError_t launch_zero(hipStream_t st, void* p, size_t bytes) {
 __global__ void __launch_bounds__(256)
 chain_setup_kernel(const int64_t* __restrict__ chain0, int G, int n_leaves, const LeafDesc* __restrict__ leaves,
                    const uint8_t* __restrict__ bits, int n_qubits, int64_t s_begin, int64_t s_range,
-                   int64_t n_chains, int64_t* __restrict__ base_table, int32_t* __restrict__ chain_b) {
+                   int64_t n_chains, int64_t gpb, int64_t* __restrict__ base_table, int32_t* __restrict__ chain_b) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= G * n_leaves) return;
   const int g = t / n_leaves, l = t - g * n_leaves;
-  const int64_t c = *chain0 + g;
+  int64_t bb, off;  // bitstring, slice offset in the range
+  if (gpb > 0) {
+    const int64_t q = *chain0 / G;
+    bb = q / gpb;
+    off = (q - bb * gpb) * G + g;
+    if (bb * s_range >= n_chains || off >= s_range) bb = -1;
+  } else {
+    const int64_t c = *chain0 + g;
+    bb = c < n_chains ? c / s_range : -1;
+    off = c - bb * s_range;
+  }
   int64_t base = 0;
   int32_t b = -1;
-  if (c < n_chains) {
-    b = (int32_t)(c / s_range);
-    const int64_t s = s_begin + (c - (int64_t)b * s_range);
+  if (bb >= 0) {
+    b = (int32_t)bb;
+    const int64_t s = s_begin + off;
     const LeafDesc& d = leaves[l];
     for (int i = 0; i < d.n_cut; ++i) base |= ((s >> d.shift[i]) & 1) << d.pos[i];
     if (d.xpos >= 0) base |= (int64_t)(bits[(int64_t)b * n_qubits + d.qubit] & 1) << d.xpos;
@@ -322,10 +332,10 @@ chain_setup_kernel(const int64_t* __restrict__ chain0, int G, int n_leaves, cons
 
 hipError_t launch_chain_setup(hipStream_t st, const int64_t* chain0, int G, int n_leaves, const LeafDesc* leaves,
                               const uint8_t* bits, int n_qubits, int64_t s_begin, int64_t s_range, int64_t n_chains,
-                              int64_t* base_table, int32_t* chain_b) {
+                              int64_t gpb, int64_t* base_table, int32_t* chain_b) {
   const int total = G * n_leaves;
   hipLaunchKernelGGL(chain_setup_kernel, dim3((total + 255) / 256), dim3(256), 0, st, chain0, G, n_leaves, leaves,
-                     bits, n_qubits, s_begin, s_range, n_chains, base_table, chain_b);
+                     bits, n_qubits, s_begin, s_range, n_chains, gpb, base_table, chain_b);
   return hipGetLastError();
 }
 

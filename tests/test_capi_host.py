@@ -268,3 +268,39 @@ def test_plan_step_info_is_consistent_with_the_plan():
     lib.qf_plan_destroy(ph)
     lib.qf_circuit_destroy(ch)
     lib.qf_ctx_destroy(ctx)
+
+
+def test_batched_plans_with_cuts_run_cut_independent_steps_once_per_group():
+    """Batched plans with cuts group chains by bitstring: steps that depend on no cut run once per
+    launch group, the others once per slice (qf_plan_flops counts the executed steps)."""
+    from workloads.circuits import generate as gen
+    from workloads.plans import plan_8x9, C5_REMOVED
+    lib, ctx = _host_ctx()
+    circ = gen(8, 9, 24, 0, C5_REMOVED)
+    plan, _ = plan_8x9(circ)
+    st, ch = _circuit(lib, ctx, circ)
+    assert st == 0
+    flops = {}
+    for G in (1, 16, 256):
+        steps = np.ascontiguousarray(np.asarray(plan["steps"], dtype=np.int32).reshape(-1))
+        carr = (_lib.qf_cut * len(plan["cuts"]))()
+        for i, c in enumerate(plan["cuts"]):
+            carr[i].q0, carr[i].q1, carr[i].bit_lo, carr[i].nbits = c
+        d = _lib.qf_plan_desc()
+        d.n_steps, d.steps = len(steps) // 2, steps.ctypes.data_as(C.POINTER(C.c_int32))
+        d.n_cuts, d.cuts, d.n_open, d.open, d.precision, d.batch = len(plan["cuts"]), carr, 0, None, 1, G
+        h = C.c_void_p()
+        assert lib.qf_plan_create(ctx, ch, C.byref(d), C.byref(h)) == 0
+        inf = _lib.qf_plan_info()
+        assert lib.qf_plan_info_get(h, C.byref(inf)) == 0
+        f = C.c_double()
+        assert lib.qf_plan_flops(h, 0, 256, C.byref(f)) == 0
+        flops[G] = f.value
+        if G == 256:
+            # per slice, only the two 3-cell strips and the three joining contractions remain
+            per_slice = inf.flops_per_slice
+            f1 = C.c_double()
+            assert lib.qf_plan_flops(h, 0, 1, C.byref(f1)) == 0
+            assert f1.value == pytest.approx(per_slice)
+            assert (f.value - per_slice) / 255 < 0.01 * per_slice
+    assert flops[256] < flops[16] < 256 * inf.flops_per_slice

@@ -44,6 +44,8 @@ def _setup_4x5():
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("G", [2, 8])
 def test_batched_equals_sequential_bitwise(ctx, precision, G):
+    """With group hoisting off, the batched path runs every step of every chain with the same
+    kernels and shapes as the one-chain path: bitwise equal."""
     import torch
     from paper_1905_00444_amd import Circuit, Plan
     _say(f"batched G={G} {precision}")
@@ -51,13 +53,44 @@ def test_batched_equals_sequential_bitwise(ctx, precision, G):
     bits = random_bitstrings(3, 20, 5)  # 3 x 16 = 48 chains: 48 / 8 leaves no tail, 48 / 32 would
     circ = Circuit(ctx, c.to_text())
     seq = Plan(ctx, circ, plan, precision, hoist=False).amplitudes(bits)
-    bat = Plan(ctx, circ, plan, precision, batch=G).amplitudes(bits)
+    bat = Plan(ctx, circ, plan, precision, batch=G, hoist=False).amplitudes(bits)
     torch.cuda.synchronize()
     assert np.array_equal(seq.cpu().numpy(), bat.cpu().numpy())
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("G", [2, 8, 32])
+def test_group_hoisting_matches_sequential_and_state_vector(ctx, precision, G):
+    """Batched plans with cuts (default): the steps that depend on no cut run once per launch
+    group, a shared operand is taken as B and the group's chains stack along M.  Different GEMM
+    shapes and operand roles accumulate in another order and split their operands in other
+    kernels, so the comparison with the one-chain path is within rounding: FP32 2e-6 norm-wise,
+    split-BF16 2e-5 (each operand is represented to about 2^-17 relative, and the two paths
+    round their splits independently); both meet the state-vector bounds."""
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    _say(f"group hoisting G={G} {precision}")
+    c, plan = _setup_4x5()
+    bits = random_bitstrings(3, 20, 5)
+    circ = Circuit(ctx, c.to_text())
+    seq = Plan(ctx, circ, plan, precision).amplitudes(bits)
+    bp = Plan(ctx, circ, plan, precision, batch=G)
+    bat = bp.amplitudes(bits)
+    torch.cuda.synchronize()
+    seq, bat = seq.cpu().numpy(), bat.cpu().numpy()
+    assert rel_err(bat, seq) <= {"fp32": 2e-6, "bf16x3": 2e-5}[precision]
+    ref = sv.open_amplitudes(c.to_text(), bits, plan["open"])
+    bound = 1e-5 if precision == "fp32" else 1e-4
+    assert rel_err(seq, ref) <= bound and rel_err(bat, ref) <= bound
+    # the executed flops count each group's cut-independent steps once
+    S = bp.info()["n_slices"]
+    assert bp.flops(0, S) < S * bp.info()["flops_per_slice"]
+
+
 def test_batched_tail_and_slice_subrange(ctx):
-    """Chains that do not fill the last group are masked; slice sub-ranges compose."""
+    """Chains that do not fill the last group are masked; slice sub-ranges compose.  Group
+    hoisting puts each bitstring's slices in groups of their own (7 slices of 3 bitstrings in
+    groups of 8: one partly idle group per bitstring)."""
     import torch
     from paper_1905_00444_amd import Circuit, Plan
     _say("batched tail")
@@ -65,13 +98,19 @@ def test_batched_tail_and_slice_subrange(ctx):
     bits = random_bitstrings(3, 20, 6)
     circ = Circuit(ctx, c.to_text())
     seq = Plan(ctx, circ, plan, "fp32", hoist=False).amplitudes(bits, 3, 10)  # 21 chains
-    bat = Plan(ctx, circ, plan, "fp32", batch=8).amplitudes(bits, 3, 10)
+    bat = Plan(ctx, circ, plan, "fp32", batch=8, hoist=False).amplitudes(bits, 3, 10)
+    hst = Plan(ctx, circ, plan, "fp32", batch=8).amplitudes(bits, 3, 10)
     torch.cuda.synchronize()
     assert np.array_equal(seq.cpu().numpy(), bat.cpu().numpy())
+    assert rel_err(hst.cpu().numpy(), seq.cpu().numpy()) <= 2e-6
     ref = sv.open_amplitudes(c.to_text(), bits, plan["open"])
-    full = Plan(ctx, circ, plan, "fp32", batch=8).amplitudes(bits)
+    full = Plan(ctx, circ, plan, "fp32", batch=8)
+    parts = full.amplitudes(bits, 0, 5)
+    full.amplitudes(bits, 5, 16, out=parts)
+    whole = full.amplitudes(bits)
     torch.cuda.synchronize()
-    assert rel_err(full.cpu().numpy(), ref) <= 1e-5
+    assert rel_err(whole.cpu().numpy(), ref) <= 1e-5
+    assert rel_err(parts.cpu().numpy(), whole.cpu().numpy()) <= 2e-6
 
 
 def test_graph_replays_match_eager(gctx):

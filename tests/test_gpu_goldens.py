@@ -64,8 +64,9 @@ def test_7x7_d40_slice_vs_fp64_oracle(ctx, precision):
 
 
 def test_70_qubit_hand_plan_path_sums_vs_fp64_oracle():
-    """All 256 slices of the two-halves hand plan for 4 of the 16 bitstrings (1024 chains, 16 per
-    launch, one captured graph on a side stream), split-BF16."""
+    """All 256 slices of the two-halves hand plan for 4 of the 16 bitstrings (1024 chains in launch
+    groups of 256 slices of one bitstring, the benchmark's configuration; one captured graph on a
+    side stream), split-BF16."""
     import torch
     from paper_1905_00444_amd import Context, Circuit, Plan
     _say("70 qubits, hand plan, 4 bitstrings x 256 slices vs FP64 oracle")
@@ -75,7 +76,7 @@ def test_70_qubit_hand_plan_path_sums_vs_fp64_oracle():
     bits = random_bitstrings(16, 70, 1)
     assert np.array_equal(g["bits"], bits)
     hand, _ = plan_8x9(circ)
-    p = Plan(ctx, Circuit(ctx, circ.to_text()), hand, "bf16x3", batch=16, graph=True)
+    p = Plan(ctx, Circuit(ctx, circ.to_text()), hand, "bf16x3", batch=256, graph=True)
     with torch.cuda.stream(p.ctx.stream):
         bt = torch.from_numpy(bits[:4]).to(p.ctx.device)
     got = p.amplitudes(bt)

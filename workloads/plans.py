@@ -253,10 +253,13 @@ C5_REMOVED = ((0, 0), (7, 8))
 
 
 def plan_8x9(circ: Circuit, depth: int = 24) -> Tuple[dict, PlanBuilder]:
-    """Two halves (columns 0-4 and 5-8) grown greedily from their removed corners and joined in
-    one last contraction; 8 cut bits on the boundary between them -> 256 slices: the whole
-    bonds (0,4)-(0,5) and (1,4)-(1,5) and the two leading bits of (2,4)-(2,5) (a partial cut,
-    paper Sec. III-A: slice sizes may be chosen adaptively).  Peak tensor 2^27."""
+    """Two halves (columns 0-4 and 5-8) joined in one last contraction; 8 cut bits on the boundary
+    between them -> 256 slices: the whole bonds (0,4)-(0,5) and (1,4)-(1,5) and the two leading
+    bits of (2,4)-(2,5) (a partial cut, paper Sec. III-A: slice sizes may be chosen adaptively).
+    Each half is grown greedily from its removed corner without the three cells that carry the
+    cut bonds; those three cells are contracted into a strip and absorbed last.  Everything but
+    the strips and the three joining contractions is the same for every slice (Sec. III-A: the
+    slices share all tensors that no cut touches).  Peak tensor 2^27."""
     qid = circ.qubit_of()
     nb = depth // 8
     cuts = []
@@ -264,10 +267,15 @@ def plan_8x9(circ: Circuit, depth: int = 24) -> Tuple[dict, PlanBuilder]:
         a, b = qid[(r, 4)], qid[(r, 5)]
         cuts.append([min(a, b), max(a, b), 0, bits])
     pb = PlanBuilder(circ, cuts, [])
-    left = [(r, c) for c in range(5) for r in range(circ.rows) if (r, c) in qid]
-    right = [(r, c) for c in range(circ.cols - 1, 4, -1) for r in range(circ.rows) if (r, c) in qid]
-    L = pb.greedy_region(left, (1, 0))
-    R = pb.greedy_region(right, (6, 8))
+    lstrip = [(0, 4), (1, 4), (2, 4)]
+    rstrip = [(0, 5), (1, 5), (2, 5)]
+    left = [(r, c) for c in range(5) for r in range(circ.rows) if (r, c) in qid and (r, c) not in lstrip]
+    right = [(r, c) for c in range(circ.cols - 1, 4, -1) for r in range(circ.rows)
+             if (r, c) in qid and (r, c) not in rstrip]
+    left_rest = pb.greedy_region(left, (1, 0))
+    right_rest = pb.greedy_region(right, (6, 8))
+    L = pb.contract(left_rest, pb.chain(lstrip))
+    R = pb.contract(right_rest, pb.chain(rstrip))
     pb.contract(L, R)
     return pb.plan(), pb
 
