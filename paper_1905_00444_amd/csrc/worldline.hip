@@ -102,9 +102,14 @@ hipError_t launch_slice_accumulate(hipStream_t st, const float2* root, int k, co
 //   diagonal D:   grad[2k+s] += lambda_s conj(f_s),   lambda_s <- conj(D[2k+s]) lambda_s
 //   projector:    lambda_{1-k} <- 0
 // Contributions are summed over all bond assignments by a block reduction and one atomic add per
-// gate and block.  States entering each gate are kept per thread (at most kMaxWlOps gates).
+// gate and block.  The states entering the gates are not stored per gate: the forward sweep keeps
+// the FP64 state entering every kGradSeg-th gate in LDS (at most kMaxWlOps gates), and the reverse
+// sweep recomputes each segment's states from its checkpoint into a register array (the same FP64
+// operations as the forward sweep), then walks the segment backwards.
 constexpr int kMaxWlOps = 160;
 constexpr int kGradThreads = 128;
+constexpr int kGradSeg = 16;
+constexpr int kGradChk = kMaxWlOps / kGradSeg;
 
 __device__ __forceinline__ float block_sum(float v, float* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -118,81 +123,106 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
   return t;
 }
 
+// Gate `in` applied to the 2-vector (v0, v1) of bond assignment idx (FP64).
+__device__ __forceinline__ void wl_apply(const WlInstr& in, const float2* g, int64_t idx, double& v0r, double& v0i,
+                                         double& v1r, double& v1i) {
+  if (in.kind == 1) {
+    const double a0r = g[0].x * v0r - g[0].y * v0i + g[1].x * v1r - g[1].y * v1i;
+    const double a0i = g[0].x * v0i + g[0].y * v0r + g[1].x * v1i + g[1].y * v1r;
+    const double a1r = g[2].x * v0r - g[2].y * v0i + g[3].x * v1r - g[3].y * v1i;
+    const double a1i = g[2].x * v0i + g[2].y * v0r + g[3].x * v1i + g[3].y * v1r;
+    v0r = a0r; v0i = a0i; v1r = a1r; v1i = a1i;
+  } else {
+    const int k = (int)((idx >> in.bitpos) & 1);
+    if (in.kind == 2) {
+      if (k == 0) { v1r = 0.0; v1i = 0.0; } else { v0r = 0.0; v0i = 0.0; }
+    } else {
+      const double d0r = g[2 * k].x, d0i = g[2 * k].y, d1r = g[2 * k + 1].x, d1i = g[2 * k + 1].y;
+      const double a0r = d0r * v0r - d0i * v0i, a0i = d0r * v0i + d0i * v0r;
+      const double a1r = d1r * v1r - d1i * v1i, a1i = d1r * v1i + d1i * v1r;
+      v0r = a0r; v0i = a0i; v1r = a1r; v1i = a1i;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kGradThreads)
 worldline_grad_kernel(const WlQubit* __restrict__ qubits, const WlInstr* __restrict__ prog,
                       const float2* __restrict__ gates, const float2* __restrict__ env,
                       float2* __restrict__ grad) {
   __shared__ float red[kGradThreads / 64];
+  __shared__ double4 chk[kGradChk][kGradThreads];  // state entering gates 0, kGradSeg, 2 kGradSeg, ...
   const WlQubit q = qubits[blockIdx.y];
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t vol = (int64_t)1 << q.nbond;
   if ((int64_t)blockIdx.x * blockDim.x >= vol) return;  // whole block idle (uniform)
   const bool active = idx < vol;
-  float4 f[kMaxWlOps];
   double v0r = 1.0, v0i = 0.0, v1r = 0.0, v1i = 0.0;
   for (int t = 0; t < q.count; ++t) {
-    f[t] = make_float4((float)v0r, (float)v0i, (float)v1r, (float)v1i);
+    if (t % kGradSeg == 0) chk[t / kGradSeg][threadIdx.x] = make_double4(v0r, v0i, v1r, v1i);
     const WlInstr in = prog[q.first + t];
-    const float2* g = gates + 4 * (int64_t)in.gate;
-    if (in.kind == 1) {
-      const double a0r = g[0].x * v0r - g[0].y * v0i + g[1].x * v1r - g[1].y * v1i;
-      const double a0i = g[0].x * v0i + g[0].y * v0r + g[1].x * v1i + g[1].y * v1r;
-      const double a1r = g[2].x * v0r - g[2].y * v0i + g[3].x * v1r - g[3].y * v1i;
-      const double a1i = g[2].x * v0i + g[2].y * v0r + g[3].x * v1i + g[3].y * v1r;
-      v0r = a0r; v0i = a0i; v1r = a1r; v1i = a1i;
-    } else {
-      const int k = (int)((idx >> in.bitpos) & 1);
-      if (in.kind == 2) {
-        if (k == 0) { v1r = 0.0; v1i = 0.0; } else { v0r = 0.0; v0i = 0.0; }
-      } else {
-        const double d0r = g[2 * k].x, d0i = g[2 * k].y, d1r = g[2 * k + 1].x, d1i = g[2 * k + 1].y;
-        const double a0r = d0r * v0r - d0i * v0i, a0i = d0r * v0i + d0i * v0r;
-        const double a1r = d1r * v1r - d1i * v1i, a1i = d1r * v1i + d1i * v1r;
-        v0r = a0r; v0i = a0i; v1r = a1r; v1i = a1i;
-      }
-    }
+    wl_apply(in, gates + 4 * (int64_t)in.gate, idx, v0r, v0i, v1r, v1i);
   }
   double l0r = 0.0, l0i = 0.0, l1r = 0.0, l1i = 0.0;
   if (active) {
     const float2 e0 = env[q.out_offset + idx], e1 = env[q.out_offset + vol + idx];
     l0r = e0.x; l0i = e0.y; l1r = e1.x; l1i = e1.y;
   }
-  for (int t = q.count - 1; t >= 0; --t) {
-    const WlInstr in = prog[q.first + t];
-    const float2* g = gates + 4 * (int64_t)in.gate;
-    const float4 fs = f[t];
-    const double f0r = fs.x, f0i = fs.y, f1r = fs.z, f1i = fs.w;
-    double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // 4 complex contributions
-    if (in.kind == 1) {
-      // c[2i + j] = lambda_i conj(f_j)
-      c[0] = l0r * f0r + l0i * f0i; c[1] = l0i * f0r - l0r * f0i;
-      c[2] = l0r * f1r + l0i * f1i; c[3] = l0i * f1r - l0r * f1i;
-      c[4] = l1r * f0r + l1i * f0i; c[5] = l1i * f0r - l1r * f0i;
-      c[6] = l1r * f1r + l1i * f1i; c[7] = l1i * f1r - l1r * f1i;
-      // lambda_j <- sum_i conj(G[i][j]) lambda_i
-      const double n0r = g[0].x * l0r + g[0].y * l0i + g[2].x * l1r + g[2].y * l1i;
-      const double n0i = g[0].x * l0i - g[0].y * l0r + g[2].x * l1i - g[2].y * l1r;
-      const double n1r = g[1].x * l0r + g[1].y * l0i + g[3].x * l1r + g[3].y * l1i;
-      const double n1i = g[1].x * l0i - g[1].y * l0r + g[3].x * l1i - g[3].y * l1r;
-      l0r = n0r; l0i = n0i; l1r = n1r; l1i = n1i;
-    } else {
-      const int k = (int)((idx >> in.bitpos) & 1);
-      if (in.kind == 2) {
-        if (k == 0) { l1r = 0.0; l1i = 0.0; } else { l0r = 0.0; l0i = 0.0; }
-      } else {
-        c[4 * k + 0] = l0r * f0r + l0i * f0i; c[4 * k + 1] = l0i * f0r - l0r * f0i;
-        c[4 * k + 2] = l1r * f1r + l1i * f1i; c[4 * k + 3] = l1i * f1r - l1r * f1i;
-        const double d0r = g[2 * k].x, d0i = g[2 * k].y, d1r = g[2 * k + 1].x, d1i = g[2 * k + 1].y;
-        const double n0r = d0r * l0r + d0i * l0i, n0i = d0r * l0i - d0i * l0r;
-        const double n1r = d1r * l1r + d1i * l1i, n1i = d1r * l1i - d1i * l1r;
-        l0r = n0r; l0i = n0i; l1r = n1r; l1i = n1i;
+  for (int sg = q.count > 0 ? (q.count - 1) / kGradSeg : -1; sg >= 0; --sg) {
+    // states entering the segment's gates, recomputed from its checkpoint
+    float4 fseg[kGradSeg];
+    {
+      const double4 w = chk[sg][threadIdx.x];
+      double w0r = w.x, w0i = w.y, w1r = w.z, w1i = w.w;
+#pragma unroll
+      for (int j = 0; j < kGradSeg; ++j) {
+        const int t = sg * kGradSeg + j;
+        fseg[j] = make_float4((float)w0r, (float)w0i, (float)w1r, (float)w1i);
+        if (t < q.count) {
+          const WlInstr in = prog[q.first + t];
+          wl_apply(in, gates + 4 * (int64_t)in.gate, idx, w0r, w0i, w1r, w1i);
+        }
       }
     }
-    if (in.kind != 2) {
-      float* out = reinterpret_cast<float*>(grad + 4 * (int64_t)in.out);
-      for (int e = 0; e < 8; ++e) {
-        const float s = block_sum(active ? (float)c[e] : 0.f, red);
-        if (threadIdx.x == 0 && s != 0.f) atomicAdd(out + e, s);
+#pragma unroll
+    for (int j = kGradSeg - 1; j >= 0; --j) {
+      const int t = sg * kGradSeg + j;
+      if (t >= q.count) continue;
+      const WlInstr in = prog[q.first + t];
+      const float2* g = gates + 4 * (int64_t)in.gate;
+      const float4 fs = fseg[j];
+      const double f0r = fs.x, f0i = fs.y, f1r = fs.z, f1i = fs.w;
+      double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // 4 complex contributions
+      if (in.kind == 1) {
+        // c[2i + j] = lambda_i conj(f_j)
+        c[0] = l0r * f0r + l0i * f0i; c[1] = l0i * f0r - l0r * f0i;
+        c[2] = l0r * f1r + l0i * f1i; c[3] = l0i * f1r - l0r * f1i;
+        c[4] = l1r * f0r + l1i * f0i; c[5] = l1i * f0r - l1r * f0i;
+        c[6] = l1r * f1r + l1i * f1i; c[7] = l1i * f1r - l1r * f1i;
+        // lambda_j <- sum_i conj(G[i][j]) lambda_i
+        const double n0r = g[0].x * l0r + g[0].y * l0i + g[2].x * l1r + g[2].y * l1i;
+        const double n0i = g[0].x * l0i - g[0].y * l0r + g[2].x * l1i - g[2].y * l1r;
+        const double n1r = g[1].x * l0r + g[1].y * l0i + g[3].x * l1r + g[3].y * l1i;
+        const double n1i = g[1].x * l0i - g[1].y * l0r + g[3].x * l1i - g[3].y * l1r;
+        l0r = n0r; l0i = n0i; l1r = n1r; l1i = n1i;
+      } else {
+        const int k = (int)((idx >> in.bitpos) & 1);
+        if (in.kind == 2) {
+          if (k == 0) { l1r = 0.0; l1i = 0.0; } else { l0r = 0.0; l0i = 0.0; }
+        } else {
+          c[4 * k + 0] = l0r * f0r + l0i * f0i; c[4 * k + 1] = l0i * f0r - l0r * f0i;
+          c[4 * k + 2] = l1r * f1r + l1i * f1i; c[4 * k + 3] = l1i * f1r - l1r * f1i;
+          const double d0r = g[2 * k].x, d0i = g[2 * k].y, d1r = g[2 * k + 1].x, d1i = g[2 * k + 1].y;
+          const double n0r = d0r * l0r + d0i * l0i, n0i = d0r * l0i - d0i * l0r;
+          const double n1r = d1r * l1r + d1i * l1i, n1i = d1r * l1i - d1i * l1r;
+          l0r = n0r; l0i = n0i; l1r = n1r; l1i = n1i;
+        }
+      }
+      if (in.kind != 2) {
+        float* out = reinterpret_cast<float*>(grad + 4 * (int64_t)in.out);
+        for (int e = 0; e < 8; ++e) {
+          const float s = block_sum(active ? (float)c[e] : 0.f, red);
+          if (threadIdx.x == 0 && s != 0.f) atomicAdd(out + e, s);
+        }
       }
     }
   }

@@ -80,6 +80,35 @@ def test_grad_4x5_d32_cuts_open_random_cotangent(ctx):
     assert rel_err(g.cpu().numpy(), ref) <= 1e-4
 
 
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16"])
+def test_grad_reduced_precision_vs_adjoint_oracle(ctx, precision):
+    """The backward pass in split-BF16 and FP16 (the same permute and GEMM kernels as the forward,
+    without renormalisation: backward plans keep true scales, and FP16 scales each GEMM's operands
+    from their largest magnitudes).  Bound: the drift reading for n contractions, applied to the
+    forward and reverse sweeps (2 n steps): 2 n 2^-16 for split-BF16, 2 n 2^-11 for FP16."""
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    _say(f"grad 4x5 d32 cuts + open, {precision}")
+    c = generate(4, 5, 32, 2)
+    text = c.to_text()
+    qid = c.qubit_of()
+    cuts = [[qid[(1, 3)], qid[(2, 3)], 0, 2], [qid[(3, 1)], qid[(3, 2)], 1, 1]]
+    plan, _ = region_plan(c, 2, 2, cuts, [(3, 4), (2, 4)])
+    bits = random_bitstrings(3, 20, 7)
+    rng = np.random.default_rng(3)
+    cot = rng.normal(size=(3, 4)) + 1j * rng.normal(size=(3, 4))
+    p = Plan(ctx, Circuit(ctx, text), plan, precision, backward=True)
+    g = p.backward(bits, cot)
+    torch.cuda.synchronize()
+    fb, fc = _expand_open(bits, plan["open"], cot)
+    ref = _oracle_grad(text, fb, fc)
+    n = len(plan["steps"])
+    bound = 2 * n * 2.0 ** (-16 if precision == "bf16x3" else -11)
+    err = rel_err(g.cpu().numpy(), ref)
+    _say(f"  rel err {err:.2e} (bound {bound:.1e})")
+    assert err <= bound
+
+
 def test_grad_6x6_d24_64_bitstrings_exact_finite_differences(ctx):
     """L = sum_b |a_b|^2 is quadratic in each gate entry: central differences are exact."""
     import torch
