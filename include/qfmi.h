@@ -153,12 +153,15 @@ typedef struct qf_plan qf_plan;
  * buffer is the caller's workspace with offsets fixed at plan time, and the stream is the
  * caller's.  Errors: QF_ERR_ARG (null out, workspace not 256-byte aligned). */
 qf_status qf_ctx_create(int device, void* hip_stream, void* workspace, size_t ws_bytes, qf_ctx** out);
+/* Replace the context's workspace or stream (same rules as qf_ctx_create; library
+ * housekeeping, no counterpart in the paper).  Errors: QF_ERR_ARG. */
 qf_status qf_ctx_set_workspace(qf_ctx* ctx, void* workspace, size_t ws_bytes);
 qf_status qf_ctx_set_stream(qf_ctx* ctx, void* hip_stream);
 /* Destroys the context.  Circuits and plans still alive are detached, not freed: destroy them
  * as usual later; every other call on them then fails with QF_ERR_ARG.  Destroying a circuit
  * likewise detaches the plans built on it. */
 void qf_ctx_destroy(qf_ctx* ctx);
+/* Text of the context's last error (owned by the context, valid until its next call). */
 const char* qf_last_error(const qf_ctx* ctx);
 
 /* Circuit on a rows x cols grid; present[r*cols+c] != 0 marks a live site (NULL = all).
@@ -170,7 +173,9 @@ const char* qf_last_error(const qf_ctx* ctx);
  * out-of-range arguments and non-adjacent qubits, QF_ERR_UNSUPPORTED for fewer than 2 qubits. */
 qf_status qf_circuit_create(qf_ctx* ctx, int rows, int cols, const uint8_t* present, int n_ops,
                             const qf_op* ops, qf_circuit** out);
-/* Replace all gate values (n_ops * 8 floats, same layout as qf_op.values). */
+/* Replace all gate values (n_ops * 8 floats, same layout as qf_op.values): the same network
+ * with other gate tensors (Sec. II), for finite differences and autograd; world-lines are
+ * rebuilt on the next call.  Errors: QF_ERR_ARG. */
 qf_status qf_circuit_set_values(qf_circuit* circ, const float* values);
 void qf_circuit_destroy(qf_circuit* circ);
 
@@ -183,17 +188,24 @@ void qf_circuit_destroy(qf_circuit* circ);
  * twice or before it exists, a root that keeps bonds, a cut off a bond or past its bits, bad open
  * qubits), QF_ERR_UNSUPPORTED (sizes beyond the library's limits).  The message says which. */
 qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* desc, qf_plan** out);
+/* Sizes of a laid-out plan (host only): slices, peak tensor, workspace bytes, and flops counted
+ * as the paper does (Sec. IV: a contraction of tensors of volumes v0, v1 into v2 costs
+ * 8 sqrt(v0 v1 v2) real flops).  Errors: QF_ERR_ARG. */
 qf_status qf_plan_info_get(const qf_plan* plan, qf_plan_info* out);
-/* Algorithmic flops (sum of 8 sqrt(v0 v1 v2) over executed steps) that qf_amplitudes performs
- * for ONE bitstring over slices [s_begin, s_end), counting the reuse of steps whose inputs do
- * not change from one slice to the next (host only). */
+/* Algorithmic flops (sum of 8 sqrt(v0 v1 v2) over executed steps, Sec. IV) that qf_amplitudes
+ * performs for ONE bitstring over slices [s_begin, s_end), counting the reuse of steps whose
+ * inputs do not change from one slice to the next (slices share every tensor that no cut
+ * touches, Sec. III-A): one chain at a time, a step reruns when a cut bit it depends on changes;
+ * batched plans with cuts run the steps that depend on no cut once per launch group of G
+ * slices (host only).  Errors: QF_ERR_ARG (bad range). */
 qf_status qf_plan_flops(const qf_plan* plan, int64_t s_begin, int64_t s_end, double* flops);
 /* Graph execution of a batched plan created with QF_PLAN_GRAPH (host only): *launches = the
  * hipGraphLaunch calls made for this plan so far (one per qf_amplitudes call), *nodes = the nodes
  * of the graph currently captured (0 before the first call).  Errors: QF_ERR_ARG (null pointer),
  * QF_ERR_HIP. */
 qf_status qf_plan_graph_info(const qf_plan* plan, int64_t* launches, int64_t* nodes);
-/* Description of step i (0 <= i < n_steps) of a laid-out plan (host only). */
+/* Description of step i (0 <= i < n_steps) of a laid-out plan: its TTGT roles and shapes
+ * (Sec. III-E) (host only).  Errors: QF_ERR_ARG. */
 qf_status qf_plan_step_info(const qf_plan* plan, int i, qf_step_info* out);
 void qf_plan_destroy(qf_plan* plan);
 
@@ -206,8 +218,9 @@ void qf_plan_destroy(qf_plan* plan);
 qf_status qf_amplitudes(qf_plan* plan, int n_batch, const uint8_t* bits_dev, int64_t s_begin,
                         int64_t s_end, double* out_dev);
 
-/* Gradients of the amplitudes with respect to every gate entry (reverse sweep over the same
- * contraction tree with the same kernels, then through each world-line).  Needs a plan created
+/* Gradients of the amplitudes with respect to every gate entry (not in the paper: the reverse
+ * sweep over the paper's contraction tree, Sec. III-A/III-D, with the same kernels, then through
+ * each world-line).  Needs a plan created
  * with QF_PLAN_BACKWARD.  For every slice in [s_begin, s_end) the forward pass is recomputed
  * and its environment tensors are propagated back.  A batched backward plan (batch G > 1, not
  * captured in a graph) runs G chains through every forward and reverse step at once; their
@@ -292,7 +305,8 @@ qf_status qf_time_cgemm_presplit(qf_ctx* ctx, int64_t M, int64_t N, int64_t K, c
 
 /* Time one launch configuration of qf_cgemm / qf_permute with HIP events on the context's
  * stream: runs `reps` launches and returns the average milliseconds per launch in *ms.
- * Synchronises the stream. */
+ * Synchronises the stream.  Measurement helpers (the paper times whole runs, Sec. IV).
+ * Errors: those of the timed call, QF_ERR_HIP. */
 qf_status qf_time_cgemm(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, const void* A,
                         const void* B, void* C, int reps, float* ms);
 qf_status qf_time_permute(qf_ctx* ctx, const void* src, void* dst, int nbits, const int32_t* perm,
@@ -322,7 +336,9 @@ qf_status qf_tuned_variant(const qf_ctx* ctx, int precision, int64_t M, int64_t 
 
 /* Event timing of the dominant kernel inside qf_amplitudes: total milliseconds and count of
  * the largest-volume GEMM launches since the last reset (measured with HIP events on the
- * context stream when enabled; enabling adds a stream synchronisation per such launch). */
+ * context stream when enabled; enabling adds a stream synchronisation per such launch).
+ * Measurement helpers: the paper reports sustained flops over the run (Sec. IV, V-B); these
+ * give the per-launch rate of the largest contraction.  Errors: QF_ERR_ARG, QF_ERR_HIP. */
 qf_status qf_profile_enable(qf_ctx* ctx, int enable);
 qf_status qf_profile_read(qf_ctx* ctx, double* gemm_ms, int64_t* gemm_launches, double* gemm_flops,
                           int reset);
