@@ -639,6 +639,10 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
       Step& st = p->steps[i];
       st.fold = !p->step_inv[i] && !st.presplit && operand_invariant(p.get(), st.B) &&
                 !operand_invariant(p.get(), st.A);
+      if (st.fold)  // split-K partials of the folded shape (G M rows, one launch)
+        p->gscratch_bytes = std::max(p->gscratch_bytes,
+                                     cgemm_split_scratch(p->precision, ((int64_t)p->G) << st.m_bits,
+                                                         (int64_t)1 << st.n_bits, (int64_t)1 << st.k_bits, 1));
     }
   }
 

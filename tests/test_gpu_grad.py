@@ -169,6 +169,41 @@ def test_autograd_function_matches_direct_backward(ctx):
     assert rel_err(vals.grad.cpu().numpy(), ref) <= 1e-4
 
 
+def test_autograd_interleaved_forwards_get_their_own_gradients(ctx):
+    """Two forwards with different gate values, then one backward through both: each branch's
+    gradient is the adjoint oracle's at that branch's values (the plan's circuit holds one set of
+    values at a time, so each backward writes its forward's values back first)."""
+    import torch
+    from paper_1905_00444_amd import Circuit, Plan
+    from paper_1905_00444_amd.autograd import QFlexAmplitudes
+    from oracle.parse import read_circuit
+    _say("autograd.Function, two interleaved forwards")
+    c = generate(3, 4, 16, 4)
+    text = c.to_text()
+    bits = random_bitstrings(6, 12, 3)
+    circ = Circuit(ctx, text)
+    p = Plan(ctx, circ, sweep_plan(c, open_qubits=[11]), "fp32", backward=True)
+    base = torch.tensor(circ.values, dtype=torch.complex64)
+    rng = np.random.default_rng(12)
+    other = base + 0.3 * torch.from_numpy((rng.normal(size=base.shape) + 1j * rng.normal(size=base.shape))
+                                          .astype(np.complex64))
+    v1 = base.clone().cuda().requires_grad_(True)
+    v2 = other.clone().cuda().requires_grad_(True)
+    a1 = QFlexAmplitudes.apply(v1, p, bits)
+    a2 = QFlexAmplitudes.apply(v2, p, bits)
+    loss = (a1.abs() ** 2).sum() + (a2.abs() ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    oc = read_circuit(text)
+    for v, a, g in ((base, a1, v1.grad), (other, a2, v2.grad)):
+        vals = [np.asarray(x).reshape(-1) for x in v.numpy().astype(np.complex128)]
+        ov = oc.with_values([x.reshape(np.shape(y)) for x, y in zip(vals, oc.values)])
+        fb, fc = _expand_open(bits, [11], 2 * a.detach().cpu().numpy())
+        ref = np.stack([np.asarray(x).reshape(4) for x in ograd.adjoint_gradient(ov, fb, fc)])
+        assert rel_err(g.cpu().numpy(), ref) <= 1e-4
+    assert rel_err(v1.grad.cpu().numpy(), v2.grad.cpu().numpy()) > 1e-2  # the two really differ
+
+
 @pytest.mark.parametrize("G", [4, 8])
 def test_batched_backward_matches_sequential_and_oracle(ctx, G):
     """Backward with G chains per launch (chains = bitstrings x slices, 3 x 8 here): equal to the
