@@ -287,21 +287,28 @@ qf_status qf_cgemm_variant(qf_ctx* ctx, int precision, int variant, int64_t M, i
  * lo = bf16(x - hi) into word 2^nbits + j: dst holds 2^(nbits+1) words = 8 * 2^nbits bytes. */
 qf_status qf_split_bf16(qf_ctx* ctx, const void* src, void* dst, int nbits);
 
-/* Split-BF16 complex GEMM on operands produced by qf_split_bf16 (A of M x K, B of N x K
- * elements, row-major, K contiguous): C[m][n] = sum_k A[m][k] B[n][k] as
- * hi*hi + hi*lo + lo*hi with FP32 accumulation, C complex64 row-major: the "G" of the paper's
- * transpose-GEMM-transpose contraction (Sec. III-E), which ran as FP32 complex GEMM; the paper
- * weighs reduced-precision inputs against the range its amplitudes need (same section), and the
- * two BF16 terms per operand keep FP32's exponent range and about 16 bits of mantissa.
- * lda / ldb: 32-bit words between consecutive rows of each plane (0 = K, dense); each operand
- * is its hi plane then its lo plane, rows * ld words each (the layout the plan's permutes
- * write, with padded rows for long K).
- * Needs powers of two with M >= 256, N >= 128, 16 <= K <= 2^20 (QF_ERR_UNSUPPORTED otherwise)
- * and K <= ld <= 2^21, a multiple of 4 (QF_ERR_ARG).  Device pointers; the caller owns every buffer. */
-qf_status qf_cgemm_presplit(qf_ctx* ctx, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
-                            void* C, int64_t lda, int64_t ldb);
-qf_status qf_time_cgemm_presplit(qf_ctx* ctx, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
-                                 void* C, int64_t lda, int64_t ldb, int reps, float* ms);
+/* FP16 operand (the conversion the FP16 pre-split GEMM consumes; the paper weighs FP16 inputs
+ * against the range its amplitudes need, Sec. III-E): dst (2^nbits 32-bit words, one plane)
+ * holds fp16 pairs (re, im) of src[j] * 2^scale_exp, round-to-nearest-even.  The plan's permutes
+ * choose scale_exp so that a tensor's largest entry lands near 2^14.  Errors: QF_ERR_ARG. */
+qf_status qf_split_f16(qf_ctx* ctx, const void* src, void* dst, int nbits, int scale_exp);
+
+/* Complex GEMM on operands converted beforehand (A of M x K, B of N x K elements, row-major, K
+ * contiguous): C[m][n] = sum_k A[m][k] B[n][k] with FP32 accumulation, C complex64 row-major: the
+ * "G" of the paper's transpose-GEMM-transpose contraction (Sec. III-E), which ran as FP32 complex
+ * GEMM; the paper weighs reduced-precision inputs against the range its amplitudes need (same
+ * section).  precision QF_BF16X3: operands from qf_split_bf16, each a hi plane then a lo plane
+ * (rows * ld words each), C = hi*hi + hi*lo + lo*hi; two BF16 terms per operand keep FP32's
+ * exponent range and about 16 bits of mantissa.  precision QF_FP16: operands from qf_split_f16,
+ * one plane each, C = A*B (the caller undoes its operand scales).  lda / ldb: 32-bit words between
+ * consecutive rows of a plane (0 = K, dense; the plan's permutes pad rows for long K).  Needs
+ * powers of two with M >= 256, N >= 128, 16 (FP16: 32) <= K <= 2^20 (QF_ERR_UNSUPPORTED
+ * otherwise) and K <= ld <= 2^21, a multiple of 4 (QF_ERR_ARG).  Device pointers; the caller owns
+ * every buffer. */
+qf_status qf_cgemm_presplit(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, const void* A,
+                            const void* B, void* C, int64_t lda, int64_t ldb);
+qf_status qf_time_cgemm_presplit(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, const void* A,
+                                 const void* B, void* C, int64_t lda, int64_t ldb, int reps, float* ms);
 
 /* Time one launch configuration of qf_cgemm / qf_permute with HIP events on the context's
  * stream: runs `reps` launches and returns the average milliseconds per launch in *ms.

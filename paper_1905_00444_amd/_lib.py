@@ -81,10 +81,12 @@ EXPORTS = {
     "qf_cgemm_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int64]),
     "qf_split_bf16": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
-    "qf_cgemm_presplit": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
-                                    C.c_int64, C.c_int64]),
-    "qf_time_cgemm_presplit": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
-                                         C.c_void_p, C.c_int64, C.c_int64, C.c_int, C.POINTER(C.c_float)]),
+    "qf_split_f16": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
+    "qf_cgemm_presplit": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_int64, C.c_int64]),
+    "qf_time_cgemm_presplit": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int,
+                                         C.POINTER(C.c_float)]),
     "qf_time_cgemm": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_int, C.POINTER(C.c_float)]),
     "qf_time_permute": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_int,

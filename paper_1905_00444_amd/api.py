@@ -317,22 +317,38 @@ def split_bf16(ctx: Context, x, out=None):
     return out
 
 
-def cgemm_presplit(ctx: Context, As, Bs, M: int, N: int, K: int, out=None, lda: int = 0, ldb: int = 0):
-    """C = A B^T from split operands (see split_bf16); lda / ldb: words between rows of a plane
-    (0: dense, K)."""
+def split_f16(ctx: Context, x, scale_exp: int = 0, out=None):
+    """FP16 form of a complex64 tensor of 2^b elements: one plane of fp16 (re, im) pairs of
+    x * 2^scale_exp (uint32 words)."""
+    torch = _torch()
+    n = x.numel()
+    b = n.bit_length() - 1
+    assert n == 1 << b and x.dtype == torch.complex64
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=x.device)
+    check(ctx.lib.qf_split_f16(ctx.h, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), b, int(scale_exp)),
+          ctx.h)
+    return out
+
+
+def cgemm_presplit(ctx: Context, As, Bs, M: int, N: int, K: int, out=None, lda: int = 0, ldb: int = 0,
+                   precision: str = "bf16x3"):
+    """C = A B^T from converted operands (split_bf16 for "bf16x3", split_f16 for "fp16");
+    lda / ldb: words between rows of a plane (0: dense, K)."""
     torch = _torch()
     if out is None:
         out = torch.empty((M, N), dtype=torch.complex64, device=As.device)
-    check(ctx.lib.qf_cgemm_presplit(ctx.h, M, N, K, C.c_void_p(As.data_ptr()), C.c_void_p(Bs.data_ptr()),
-                                    C.c_void_p(out.data_ptr()), lda, ldb), ctx.h)
+    check(ctx.lib.qf_cgemm_presplit(ctx.h, PRECISIONS[precision], M, N, K, C.c_void_p(As.data_ptr()),
+                                    C.c_void_p(Bs.data_ptr()), C.c_void_p(out.data_ptr()), lda, ldb), ctx.h)
     return out
 
 
 def time_cgemm_presplit(ctx: Context, As, Bs, C_out, M: int, N: int, K: int, reps: int = 5, lda: int = 0,
-                        ldb: int = 0) -> float:
+                        ldb: int = 0, precision: str = "bf16x3") -> float:
     ms = C.c_float()
-    check(ctx.lib.qf_time_cgemm_presplit(ctx.h, M, N, K, C.c_void_p(As.data_ptr()), C.c_void_p(Bs.data_ptr()),
-                                         C.c_void_p(C_out.data_ptr()), lda, ldb, reps, C.byref(ms)), ctx.h)
+    check(ctx.lib.qf_time_cgemm_presplit(ctx.h, PRECISIONS[precision], M, N, K, C.c_void_p(As.data_ptr()),
+                                         C.c_void_p(Bs.data_ptr()), C.c_void_p(C_out.data_ptr()), lda, ldb, reps,
+                                         C.byref(ms)), ctx.h)
     return ms.value
 
 

@@ -1,14 +1,17 @@
-// Split-BF16 complex GEMM on operands split by the preceding permute (paper Sec. III-E, the
-// "G" of transpose-GEMM-transpose; see cgemm.hip for the real embedding and the split).
+// Split-BF16 and scaled-FP16 complex GEMMs on operands converted by the preceding permute (paper
+// Sec. III-E, the "G" of transpose-GEMM-transpose; see cgemm.hip for the real embedding, the split
+// and the FP16 scaling).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include "cgemm_common.h"
 
 namespace qf {
 
-// Large shapes, split-BF16 on operands already split in HBM (hi and lo planes of bfloat16
-// complex numbers, [rows][K] each, written by the permute that precedes the GEMM).  A 256 x 128
-// complex block per workgroup, 8 waves, K-tiles of 16 complex.  The operands travel HBM -> LDS
+// Large shapes on operands already converted in HBM by the permute that precedes the GEMM:
+// split-BF16 (hi and lo planes of bfloat16 complex numbers, [rows][K] each; K-tiles of 16 complex,
+// the two planes of a tile staged side by side) or FP16 scaled to the operand's magnitude (one
+// plane [rows][K] of fp16 complex numbers; K-tiles of 32 complex, staged as two 16-complex halves
+// in the places of the two planes).  A 256 x 128 complex block per workgroup, 8 waves.  The operands travel HBM -> LDS
 // directly (buffer_load_dwordx4 ... lds: each lane moves 16 bytes, one instruction fills 1 KiB =
 // 16 rows x 64 bytes of one plane) through a ring of 3 LDS stages.  The four 16-byte chunks of a
 // row are stored in the order c ^ ((row >> 1) & 3): a 16-byte LDS read serves 8 lanes per pass,
@@ -24,7 +27,11 @@ namespace qf {
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 constexpr int kPsThreads = 512;
-constexpr int kPsBM = 256, kPsBN = 128, kPsBK = 16;
+constexpr int kPsBM = 256, kPsBN = 128;
+// complex elements of K per tile, and byte offset of the second staged half within a row:
+// split-BF16 stages hi and lo of 16 complex (separate planes), FP16 two 16-complex halves of a row
+template <int PREC> struct PsTile { static constexpr int BK = 16, half_off = 0; };
+template <> struct PsTile<P_FP16> { static constexpr int BK = 32, half_off = 64; };
 constexpr int kPsPlaneA = kPsBM * 64;                      // 16 KiB
 constexpr int kPsPlaneB = kPsBN * 64;                      // 8 KiB
 constexpr int kPsStage = 2 * kPsPlaneA + 2 * kPsPlaneB;    // 48 KiB
@@ -48,16 +55,17 @@ struct PsLoader {
   int la0, la1, lb;                       // LDS offsets of the chunks within a stage
 };
 
+template <int HOFF>
 __device__ __forceinline__ void ps_issue(const PsLoader& L, char* stage, int kbytes) {
   __builtin_amdgcn_raw_ptr_buffer_load_lds(L.ah, (lds_ptr_t)(stage + L.la0), 16, L.va, L.ra0 + kbytes, 0, 0);
   __builtin_amdgcn_raw_ptr_buffer_load_lds(L.ah, (lds_ptr_t)(stage + L.la1), 16, L.va, L.ra1 + kbytes, 0, 0);
-  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.al, (lds_ptr_t)(stage + kPsPlaneA + L.la0), 16, L.va, L.ra0 + kbytes,
-                                           0, 0);
-  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.al, (lds_ptr_t)(stage + kPsPlaneA + L.la1), 16, L.va, L.ra1 + kbytes,
-                                           0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.al, (lds_ptr_t)(stage + kPsPlaneA + L.la0), 16, L.va,
+                                           L.ra0 + kbytes + HOFF, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.al, (lds_ptr_t)(stage + kPsPlaneA + L.la1), 16, L.va,
+                                           L.ra1 + kbytes + HOFF, 0, 0);
   __builtin_amdgcn_raw_ptr_buffer_load_lds(L.bh, (lds_ptr_t)(stage + L.lb), 16, L.vb, L.rb + kbytes, 0, 0);
-  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.bl, (lds_ptr_t)(stage + kPsPlaneB + L.lb), 16, L.vb, L.rb + kbytes, 0,
-                                           0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(L.bl, (lds_ptr_t)(stage + kPsPlaneB + L.lb), 16, L.vb,
+                                           L.rb + kbytes + HOFF, 0, 0);
 }
 
 // A and B fragments of one K-tile (both planes) into registers; B expanded into the real column
@@ -87,10 +95,25 @@ __device__ __forceinline__ void ps_read(const char* st, int wr, int wc, int l16,
     }
 }
 
-// The products of one K-tile for every accumulator: lo x hi, hi x lo, then hi x hi, so the
-// largest product is added last.
+// The products of one K-tile for every accumulator.  Split-BF16: lo x hi, hi x lo, then hi x hi,
+// so the largest product is added last.  FP16: the first 16-complex half, then the second.
+template <int PREC>
 __device__ __forceinline__ void ps_multiply(const u4 (&ah)[kPsWI], const u4 (&al)[kPsWI], const u4 (&bh)[kPsWJ],
                                             const u4 (&bl)[kPsWJ], f4 (&acc)[kPsWI][kPsWJ]) {
+  if constexpr (PREC == P_FP16) {
+#pragma unroll
+    for (int i = 0; i < kPsWI; ++i) {
+#pragma unroll
+      for (int j = 0; j < kPsWJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, ah[i]), __builtin_bit_cast(h8, bh[j]),
+                                                           acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < kPsWJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, al[i]), __builtin_bit_cast(h8, bl[j]),
+                                                           acc[i][j], 0, 0, 0);
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < kPsWI; ++i) {
     const bf8 a_h = __builtin_bit_cast(bf8, ah[i]);
@@ -114,6 +137,7 @@ __device__ __forceinline__ void ps_barrier() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
+template <int PREC>
 __global__ void __launch_bounds__(kPsThreads)
 cgemm_pingpong_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restrict__ Ah,
                         const uint32_t* __restrict__ Al, const uint32_t* __restrict__ Bh,
@@ -175,9 +199,10 @@ cgemm_pingpong_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restr
     for (int j = 0; j < kPsWJ; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
   u4 ah[kPsWI], al[kPsWI], bh[kPsWJ], bl[kPsWJ];
 
-  const int nk = (int)(K / kPsBK);
-  ps_issue(L, lds, 0);
-  if (nk > 1) ps_issue(L, lds + kPsStage, kPsBK * 4);
+  constexpr int BK = PsTile<PREC>::BK, HOFF = PsTile<PREC>::half_off;
+  const int nk = (int)(K / BK);
+  ps_issue<HOFF>(L, lds, 0);
+  if (nk > 1) ps_issue<HOFF>(L, lds + kPsStage, BK * 4);
   if (nk > 1) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
   else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   ps_barrier();
@@ -190,12 +215,12 @@ cgemm_pingpong_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restr
   int s_cur = 0;  // stage of tile t
   for (int t = 0; t < nk; ++t) {
     const int s_t2 = s_cur == 0 ? kPsStages - 1 : s_cur - 1;  // stage of tile t + 2
-    if (t + 2 < nk) ps_issue(L, lds + s_t2 * kPsStage, (t + 2) * kPsBK * 4);
+    if (t + 2 < nk) ps_issue<HOFF>(L, lds + s_t2 * kPsStage, (t + 2) * BK * 4);
     ps_read(lds + s_cur * kPsStage, wr, wc, l16, lg, a_chunk, bx, ah, al, bh, bl);
     if (t + 2 < nk) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)" ::: "memory");
     else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
     ps_barrier();
-    ps_multiply(ah, al, bh, bl, acc);
+    ps_multiply<PREC>(ah, al, bh, bl, acc);
     ps_barrier();
     s_cur = s_cur == kPsStages - 1 ? 0 : s_cur + 1;
   }
@@ -203,7 +228,7 @@ cgemm_pingpong_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restr
 
   // renormalisation is read only now, so that nothing else is in flight during the load ring
   float scale_a, scale_b, unscale;
-  renorm_begin<P_BF16X3>(rn, nullptr, nullptr, scale_a, scale_b, unscale);
+  renorm_begin<PREC>(rn, nullptr, nullptr, scale_a, scale_b, unscale);
   float mx = 0.f;
 #pragma unroll
   for (int i = 0; i < kPsWI; ++i)
@@ -224,18 +249,21 @@ cgemm_pingpong_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restr
   if (rn.c) record_amax(rn.c, mx);
 }
 
-bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K) {
+bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K, int precision) {
   auto p2 = [](int64_t x) { return x > 0 && (x & (x - 1)) == 0; };
-  return p2(M) && p2(N) && p2(K) && M >= kPsBM && N >= kPsBN && K >= kPsBK && K + 64 <= kPsMaxLd;
+  const int bk = precision == P_FP16 ? PsTile<P_FP16>::BK : PsTile<P_BF16X3>::BK;
+  return (precision == P_BF16X3 || precision == P_FP16) && p2(M) && p2(N) && p2(K) && M >= kPsBM &&
+         N >= kPsBN && K >= bk && K + 64 <= kPsMaxLd;
 }
 
-// A, B: split operands, each a hi plane followed by a lo plane (rows x K bfloat16 pairs each,
+// Split-BF16: A, B each a hi plane followed by a lo plane (rows x K bfloat16 pairs each,
 // consecutive rows lda (ldb) words apart, the lo plane rows * lda (rows * ldb) words after the hi
-// plane), batch strides in complex elements of one plane-pair (= rows * ld).
+// plane), batch strides in complex elements of one plane-pair (= rows * ld).  FP16: one plane of
+// rows x K fp16 pairs (rows lda / ldb words apart), batch strides in 32-bit words.
 hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
                                  float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc, const Renorm& rn,
-                                 int64_t lda, int64_t ldb) {
-  if (!cgemm_presplit_fits(M, N, K)) return hipErrorInvalidValue;
+                                 int64_t lda, int64_t ldb, int precision) {
+  if (!cgemm_presplit_fits(M, N, K, precision)) return hipErrorInvalidValue;
   if (lda == 0) lda = K;
   if (ldb == 0) ldb = K;
   if (lda < K || ldb < K || (lda & 3) || (ldb & 3) || lda > kPsMaxLd || ldb > kPsMaxLd) return hipErrorInvalidValue;
@@ -245,12 +273,16 @@ hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K
   }
   const uint32_t* a = reinterpret_cast<const uint32_t*>(A);
   const uint32_t* b = reinterpret_cast<const uint32_t*>(B);
-  const uint32_t* al = a + M * lda;
-  const uint32_t* bl = b + N * ldb;
   const int64_t tiles = (M / kPsBM) * (N / kPsBN);
   const dim3 grid((unsigned)tiles, 1, (unsigned)batch);
-  hipLaunchKernelGGL(cgemm_pingpong_presplit, grid, dim3(kPsThreads), 0, st, M, N, K, a, al, b, bl, C, lda, ldb,
-                     2 * sa, 2 * sb, sc, rn);
+  if (precision == P_FP16) {
+    // the second staged half of a tile is the same row 16 complex further (half_off)
+    hipLaunchKernelGGL(cgemm_pingpong_presplit<P_FP16>, grid, dim3(kPsThreads), 0, st, M, N, K, a, a, b, b, C, lda,
+                       ldb, sa, sb, sc, rn);
+  } else {
+    hipLaunchKernelGGL(cgemm_pingpong_presplit<P_BF16X3>, grid, dim3(kPsThreads), 0, st, M, N, K, a, a + M * lda, b,
+                       b + N * ldb, C, lda, ldb, 2 * sa, 2 * sb, sc, rn);
+  }
   return hipGetLastError();
 }
 

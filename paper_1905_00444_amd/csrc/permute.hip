@@ -16,7 +16,7 @@
 #include <stdlib.h>
 #include <algorithm>
 #include <vector>
-#include "qf_kernels.h"
+#include "cgemm_common.h"
 
 namespace qf {
 
@@ -44,12 +44,8 @@ struct PermKernelArgs {
   int split_kbits;          // padded split rows: row = index >> split_kbits, ...
   int64_t split_ld;         // ... at split_ld words apart (0: dense)
   int64_t split_plane;      // words from the hi plane to the lo plane
+  const NodeScale* f16_scale;  // split == 2: scale exponent source (see PermuteArgs)
 };
-
-__device__ __forceinline__ uint32_t bf16_pair(float re, float im) {
-  const __bf16 a = (__bf16)re, b = (__bf16)im;
-  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
-}
 
 __device__ __forceinline__ int lds_index(int u) { return u + (u >> 5); }
 
@@ -94,6 +90,7 @@ permute_kernel(const float2* __restrict__ src, float2* __restrict__ dst, PermKer
     }
   }
   __syncthreads();
+  const float f16s = (a.split == 2 && a.f16_scale) ? ldexpf(1.f, 14 - renorm_exp(a.f16_scale)) : 1.f;
   for (int it = 0; tid < tvol && it < iters; ++it) {
     int u = u_lo;
     int64_t off = w_lo;
@@ -106,16 +103,23 @@ permute_kernel(const float2* __restrict__ src, float2* __restrict__ dst, PermKer
     float2 x = tile[lds_index(u)];
     x.x *= a.scale;
     x.y *= a.scale * a.conj_sign;
-    if (a.split) {
+    if (a.split == 2) {
+      // one plane of fp16 pairs scaled so that the tensor's largest entry lands near 2^14
+      uint32_t* w = reinterpret_cast<uint32_t*>(dst);
+      int64_t idx = dbase + off;
+      if (a.split_ld)
+        idx = (idx >> a.split_kbits) * a.split_ld + (idx & (((int64_t)1 << a.split_kbits) - 1));
+      w[idx] = pack_f16x2(x.x * f16s, x.y * f16s);
+    } else if (a.split) {
       // hi plane at word idx, lo plane split_plane words further, in this batch element
       uint32_t* w = reinterpret_cast<uint32_t*>(dst);
       int64_t idx = dbase + off;
       if (a.split_ld)
         idx = (idx >> a.split_kbits) * a.split_ld + (idx & (((int64_t)1 << a.split_kbits) - 1));
-      const uint32_t hi = bf16_pair(x.x, x.y);
+      const uint32_t hi = pack_bf16x2(x.x, x.y);
       const float hr = __uint_as_float(hi << 16), hiim = __uint_as_float(hi & 0xffff0000u);
       w[idx] = hi;
-      w[a.split_plane + idx] = bf16_pair(x.x - hr, x.y - hiim);
+      w[a.split_plane + idx] = pack_bf16x2(x.x - hr, x.y - hiim);
     } else {
       dst[dbase + off] = x;
     }
@@ -169,6 +173,7 @@ hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const 
   a.split_kbits = p.split_kbits;
   a.split_ld = p.split_ld;
   a.split_plane = p.split_ld ? (((int64_t)1 << (b - p.split_kbits)) * p.split_ld) : ((int64_t)1 << b);
+  a.f16_scale = p.f16_scale;
   const int64_t tiles = (int64_t)1 << no;
   const unsigned gx = (unsigned)std::min<int64_t>(tiles, 65536);
   const unsigned gy = (unsigned)(tiles / gx);

@@ -68,6 +68,10 @@ struct PermuteArgs {
   // words after the hi plane (split_ld = 0: dense planes)
   int split_kbits = 0;
   int64_t split_ld = 0;
+  // split == 2: one plane of fp16 (re, im) pairs instead, each value times 2^(14 - e) where e is
+  // the binary exponent of f16_scale->amax (the scale lands the tensor's largest entry near 2^14;
+  // null: times 1), after `scale`
+  const NodeScale* f16_scale = nullptr;
 };
 hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& a);
 
@@ -118,11 +122,13 @@ hipError_t launch_slice_accumulate_batched(hipStream_t st, const float2* root, i
 // *chain0 = value (add = 0) or *chain0 += value (add = 1), as a kernel (graph-capturable).
 hipError_t launch_chain_counter(hipStream_t st, int64_t* chain0, int64_t value, int add);
 
-// Split-BF16 GEMM on operands split by the permute (hi plane then lo plane per batch element).
-bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K);
+// Split-BF16 GEMM on operands split by the permute (hi plane then lo plane per batch element), or
+// FP16 GEMM on operands scaled and converted by the permute (one plane); precision P_BF16X3 / P_FP16
+// (cgemm_common.h), 1 / 2 as qf_precision.
+bool cgemm_presplit_fits(int64_t M, int64_t N, int64_t K, int precision = 1);
 hipError_t launch_cgemm_presplit(hipStream_t st, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
                                  float2* C, int64_t batch, int64_t sa, int64_t sb, int64_t sc,
-                                 const Renorm& rn = Renorm{}, int64_t lda = 0, int64_t ldb = 0);
+                                 const Renorm& rn = Renorm{}, int64_t lda = 0, int64_t ldb = 0, int precision = 1);
 
 // Batched complex GEMM, C[m][n] = sum_k A[m][k] B[n][k].
 hipError_t launch_cgemm(hipStream_t st, int precision, int64_t M, int64_t N, int64_t K,

@@ -594,8 +594,10 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     st.k_bits = (int)K.size();
     st.m_bits = xf;
     st.n_bits = yf;
-    st.presplit = p->precision == QF_BF16X3 && !p->backward &&
-                  cgemm_presplit_fits((int64_t)1 << xf, (int64_t)1 << yf, (int64_t)1 << K.size());
+    // large steps run on operands that their permutes convert once: split into bfloat16 hi and lo
+    // planes (split-BF16), or scaled to fp16 from the operand's renormalisation exponent (FP16)
+    st.presplit = !p->backward && (p->precision == QF_BF16X3 || (p->precision == QF_FP16 && p->renorm)) &&
+                  cgemm_presplit_fits((int64_t)1 << xf, (int64_t)1 << yf, (int64_t)1 << K.size(), p->precision);
     if (st.presplit) {
       for (Operand* op : {&st.A, &st.B}) {
         if (!op->permute) p->permute_bytes += 16.0 * std::ldexp(1.0, op->nbits);
@@ -923,6 +925,19 @@ static void leaf_args(const qf_plan* p, const Node& nd, const Operand& op, const
   }
 }
 
+static NodeScale* node_scale(qf_plan* p, int node) {
+  return reinterpret_cast<NodeScale*>(p->ctx->ws + p->off_scales) + node;
+}
+
+// Conversion that an operand's permute applies for a pre-split GEMM: bfloat16 hi and lo planes
+// (split-BF16), or one fp16 plane scaled from the operand's renormalisation exponent (FP16).
+static void set_split(qf_plan* p, const Operand& op, PermuteArgs* a) {
+  a->split = op.split ? (p->precision == QF_FP16 ? 2 : 1) : 0;
+  a->split_kbits = op.kbits;
+  a->split_ld = op.split ? op.ld : 0;
+  a->f16_scale = (op.split && p->precision == QF_FP16) ? node_scale(p, op.node) : nullptr;
+}
+
 static qf_status run_operand(qf_plan* p, const Operand& op, const uint8_t* bits_row, int64_t s, const float2** ptr) {
   qf_ctx* c = p->ctx;
   const Node& nd = p->nodes[op.node];
@@ -942,17 +957,11 @@ static qf_status run_operand(qf_plan* p, const Operand& op, const uint8_t* bits_
     a.scale = 1.0f;
     src = wsp(c, nd.offset);
   }
-  a.split = op.split ? 1 : 0;
-  a.split_kbits = op.kbits;
-  a.split_ld = op.split ? op.ld : 0;
+  set_split(p, op, &a);
   float2* dst = wsp(c, op.buf);
   QF_HIP(c, launch_permute(c->stream, src, dst, a));
   *ptr = dst;
   return QF_OK;
-}
-
-static NodeScale* node_scale(qf_plan* p, int node) {
-  return reinterpret_cast<NodeScale*>(p->ctx->ws + p->off_scales) + node;
 }
 
 // Renormalisation slots of step i's operands and result (all null when the plan stores true scales).
@@ -1050,7 +1059,8 @@ static qf_status run_step(qf_plan* p, size_t i, const uint8_t* row, int64_t s) {
   const Renorm rn = step_renorm(p, i);
   if (st.presplit) {
     const int64_t lda = split_ld(st.A), ldb = split_ld(st.B);
-    QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, 1, M * lda, N * ldb, M * N, rn, lda, ldb));
+    QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, 1, M * lda, N * ldb, M * N, rn, lda, ldb,
+                                    p->precision));
   } else {
     e = plan_gemm(p, M, N, K, A, B, C, 1, rn);
     if (e != QF_OK) return e;
@@ -1104,9 +1114,7 @@ static qf_status run_operand_batched(qf_plan* p, const Operand& op, const float2
     src = wsp(c, nd.offset);
     a.src_bstride = (int64_t)1 << nd.labels.size();
   }
-  a.split = op.split ? 1 : 0;
-  a.split_kbits = op.kbits;
-  a.split_ld = op.split ? op.ld : 0;
+  set_split(p, op, &a);
   float2* dst = wsp(c, op.buf);
   QF_HIP(c, launch_permute(c->stream, src, dst, a));
   *ptr = dst;
@@ -1145,7 +1153,7 @@ static qf_status enqueue_group(qf_plan* p, const uint8_t* bits_dev, int64_t s_be
     if (st.presplit) {
       const int64_t lda = split_ld(st.A), ldb = split_ld(st.B);
       QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, Gi, shared_a ? 0 : M * lda, shared_b ? 0 : N * ldb,
-                                      M * N, rn, lda, ldb));
+                                      M * N, rn, lda, ldb, p->precision));
     } else {
       // folded: the group's per-chain A matrices are consecutive, so with B shared they form one
       // A of G M rows and the product's rows are the chains' results in order
@@ -1628,31 +1636,47 @@ qf_status qf_split_bf16(qf_ctx* c, const void* src, void* dst, int nbits) {
   return QF_OK;
 }
 
-qf_status qf_cgemm_presplit(qf_ctx* c, int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C,
-                            int64_t lda, int64_t ldb) {
+qf_status qf_split_f16(qf_ctx* c, const void* src, void* dst, int nbits, int scale_exp) {
+  if (!c || !src || !dst || nbits < 0 || nbits > 40 || scale_exp < -126 || scale_exp > 127)
+    return fail(c, QF_ERR_ARG, "qf_split_f16: bad arguments");
+  PermuteArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nbits = nbits;
+  for (int i = 0; i < nbits; ++i) a.perm[i] = i;
+  a.scale = std::ldexp(1.0f, scale_exp);
+  a.split = 2;
+  QF_HIP(c, launch_permute(c->stream, reinterpret_cast<const float2*>(src), reinterpret_cast<float2*>(dst), a));
+  return QF_OK;
+}
+
+qf_status qf_cgemm_presplit(qf_ctx* c, int precision, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
+                            void* C, int64_t lda, int64_t ldb) {
   if (!c || !A || !B || !C) return fail(c, QF_ERR_ARG, "qf_cgemm_presplit: null pointer");
-  if (!cgemm_presplit_fits(M, N, K))
-    return fail(c, QF_ERR_UNSUPPORTED, "qf_cgemm_presplit needs powers of two with M >= 256, N >= 128, 16 <= K <= 2^20");
+  if (precision != QF_BF16X3 && precision != QF_FP16)
+    return fail(c, QF_ERR_ARG, "qf_cgemm_presplit: precision must be QF_BF16X3 or QF_FP16");
+  if (!cgemm_presplit_fits(M, N, K, precision))
+    return fail(c, QF_ERR_UNSUPPORTED, "qf_cgemm_presplit needs powers of two with M >= 256, N >= 128, "
+                                       "16 (FP16: 32) <= K <= 2^20");
   if (lda == 0) lda = K;
   if (ldb == 0) ldb = K;
   if (lda < K || ldb < K || (lda & 3) || (ldb & 3) || lda > ((int64_t)1 << 21) || ldb > ((int64_t)1 << 21))
     return fail(c, QF_ERR_ARG, "qf_cgemm_presplit: row pitches must be >= K, <= 2^21 and multiples of 4 words");
   QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, reinterpret_cast<float2*>(C), 1, M * lda, N * ldb, M * N,
-                                  Renorm{}, lda, ldb));
+                                  Renorm{}, lda, ldb, precision));
   return QF_OK;
 }
 
-qf_status qf_time_cgemm_presplit(qf_ctx* c, int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C,
-                                 int64_t lda, int64_t ldb, int reps, float* ms) {
+qf_status qf_time_cgemm_presplit(qf_ctx* c, int precision, int64_t M, int64_t N, int64_t K, const void* A,
+                                 const void* B, void* C, int64_t lda, int64_t ldb, int reps, float* ms) {
   if (!c || !ms || reps < 1) return QF_ERR_ARG;
-  qf_status st = qf_cgemm_presplit(c, M, N, K, A, B, C, lda, ldb);
+  qf_status st = qf_cgemm_presplit(c, precision, M, N, K, A, B, C, lda, ldb);
   if (st != QF_OK) return st;
   hipEvent_t e0, e1;
   QF_HIP(c, hipEventCreate(&e0));
   QF_HIP(c, hipEventCreate(&e1));
   QF_HIP(c, hipEventRecord(e0, c->stream));
   for (int i = 0; i < reps; ++i) {
-    st = qf_cgemm_presplit(c, M, N, K, A, B, C, lda, ldb);
+    st = qf_cgemm_presplit(c, precision, M, N, K, A, B, C, lda, ldb);
     if (st != QF_OK) return st;
   }
   QF_HIP(c, hipEventRecord(e1, c->stream));

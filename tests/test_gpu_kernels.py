@@ -215,7 +215,7 @@ def test_cgemm_presplit_matches_numpy(ctx, M, N, K):
     bound = np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64).T
     As = split_bf16(ctx, torch.from_numpy(A).cuda().reshape(-1))
     Bs = split_bf16(ctx, torch.from_numpy(B).cuda().reshape(-1))
-    Cg = cgemm_presplit(ctx, As, Bs, M, N, K)
+    Cg = cgemm_presplit(ctx, As, Bs, M, N, K, precision="bf16x3")
     torch.cuda.synchronize()
     err = np.max(np.abs(Cg.cpu().numpy().astype(np.complex128) - ref) / bound)
     assert err <= TOL["bf16x3"], err
@@ -359,3 +359,58 @@ def test_permute_2_30_elements_sampled_bit_exact(ctx):
     got = dst[torch.from_numpy(j).cuda()].cpu().numpy()
     want = src[torch.from_numpy(idx).cuda()].cpu().numpy()
     assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_split_f16_matches_torch_rounding(ctx):
+    """qf_split_f16: fp16(x * 2^s) for re and im, round-to-nearest-even, bit-exact vs torch."""
+    import torch
+    from paper_1905_00444_amd import split_f16
+    _say("split f16")
+    rng = np.random.default_rng(12)
+    x = _rand_c64(rng, 2 ** 14) * np.float32(3.7)
+    for s in (0, 5, -3):
+        w = split_f16(ctx, torch.from_numpy(x).cuda(), s)
+        torch.cuda.synchronize()
+        w = w.cpu().numpy().view(np.uint32)
+        f = np.float32(2.0 ** s)
+        re = torch.from_numpy(x.real * f).to(torch.float16).view(torch.int16).numpy().view(np.uint16)
+        im = torch.from_numpy(x.imag * f).to(torch.float16).view(torch.int16).numpy().view(np.uint16)
+        assert np.array_equal(w & 0xFFFF, re.astype(np.uint32)) and np.array_equal(w >> 16, im.astype(np.uint32))
+
+
+@pytest.mark.parametrize("M,N,K,pad", [(256, 128, 32, 0), (512, 256, 64, 0), (1024, 512, 2048, 0),
+                                       (2048, 1024, 512, 0), (512, 256, 8192, 64), (256, 512, 32768, 64)])
+def test_cgemm_presplit_f16_matches_numpy(ctx, M, N, K, pad):
+    """The FP16 pre-split kernel (operands converted once by qf_split_f16; K-tiles of 32 complex
+    staged as two halves), dense and with padded rows (NaN pads), against numpy complex128."""
+    import torch
+    from paper_1905_00444_amd import split_f16, cgemm_presplit
+    _say(f"cgemm presplit fp16 {M}x{N}x{K} pad {pad}")
+    rng = np.random.default_rng(M + 5 * N + K)
+    A = _rand_c64(rng, (M, K))
+    B = _rand_c64(rng, (N, K))
+    ref = A.astype(np.complex128) @ B.astype(np.complex128).T
+    bound = np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64).T
+    ld = K + pad
+    Af = split_f16(ctx, torch.from_numpy(A).cuda().reshape(-1))
+    Bf = split_f16(ctx, torch.from_numpy(B).cuda().reshape(-1))
+    if pad:
+        Ap = torch.full((M, ld), 0x7E007E00, dtype=torch.int32, device="cuda")
+        Bp = torch.full((N, ld), 0x7E007E00, dtype=torch.int32, device="cuda")
+        Ap[:, :K] = Af.view(M, K)
+        Bp[:, :K] = Bf.view(N, K)
+        Af, Bf = Ap, Bp
+    Cg = cgemm_presplit(ctx, Af, Bf, M, N, K, lda=ld, ldb=ld, precision="fp16")
+    torch.cuda.synchronize()
+    got = Cg.cpu().numpy().astype(np.complex128)
+    assert np.all(np.isfinite(got))
+    err = np.max(np.abs(got - ref) / bound)
+    assert err <= TOL["fp16"], err
+
+
+def test_cgemm_presplit_f16_rejects_short_k(ctx):
+    import torch
+    from paper_1905_00444_amd import cgemm_presplit
+    z = torch.zeros(256 * 16, dtype=torch.int32, device="cuda")
+    with pytest.raises(RuntimeError):
+        cgemm_presplit(ctx, z, z[:128 * 16], 256, 128, 16, precision="fp16")
