@@ -40,7 +40,7 @@ typedef enum {
   QF_ERR_PLAN = -2,        /* invalid contraction plan or cut */
   QF_ERR_WORKSPACE = -3,   /* workspace too small: see qf_plan_info().workspace_bytes */
   QF_ERR_HIP = -4,         /* a HIP runtime call failed; message holds hipGetErrorString */
-  QF_ERR_UNSUPPORTED = -5, /* valid request this build does not support */
+  QF_ERR_UNSUPPORTED = -5, /* valid request that the library does not support */
   QF_ERR_INJECTED = -6     /* fault injected through QFMI_FAULT_AFTER_SLICES (testing) */
 } qf_status;
 
