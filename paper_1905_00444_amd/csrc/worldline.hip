@@ -56,7 +56,7 @@ hipError_t launch_worldlines(hipStream_t st, const WlQubit* qubits, int n_qubits
   return hipGetLastError();
 }
 
-// Slice sum (paper Sec. III-A: the amplitude is the sum of all path contributions), FP64:
+// Slice sum (paper Sec. III-A: an amplitude adds up the contributions of every cut-bond assignment), FP64:
 // out[j] += root[sum_t bit_t(j) << pos[t]] for j < 2^k, bit k-1-t of j <-> open qubit t.
 struct AccArgs {
   int k;

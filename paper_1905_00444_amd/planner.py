@@ -1,8 +1,8 @@
 """Automatic choice of cuts and contraction order for grid circuits (paper Sec. III-D).
 
 Finding the best cuts and order is NP-hard in general; for planar grids the paper splits the
-circuit into pieces with a small shared boundary, cuts bonds on that boundary, and prefers a few
-large, high-arithmetic-intensity contractions over many small ones.  This module searches that
+circuit into pieces with a small shared boundary, cuts bonds on that boundary, and favours orders
+whose work sits in a handful of big contractions with many flops per byte moved.  This module searches that
 family and ranks candidates by a time model, not by flop count alone:
 
 * Orders.  Quadrant splits at (row r0, column c0): regions A (top-left), B (top-right), D
