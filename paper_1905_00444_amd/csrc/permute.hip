@@ -49,6 +49,36 @@ struct PermKernelArgs {
 
 __device__ __forceinline__ int lds_index(int u) { return u + (u >> 5); }
 
+// Store of one permuted element at destination index idx: complex64, or the split forms that a
+// pre-split GEMM reads (SPLIT 1: bf16 hi plane and bf16 lo plane; SPLIT 2: one plane of scaled
+// fp16 pairs), with padded rows when split_ld is set.
+template <int SPLIT>
+__device__ __forceinline__ void perm_store(float2* __restrict__ dst, const PermKernelArgs& a, int64_t idx, float2 x,
+                                           float f16s) {
+  if constexpr (SPLIT == 0) {
+    dst[idx] = x;
+  } else {
+    uint32_t* w = reinterpret_cast<uint32_t*>(dst);
+    if (a.split_ld) idx = (idx >> a.split_kbits) * a.split_ld + (idx & (((int64_t)1 << a.split_kbits) - 1));
+    if constexpr (SPLIT == 2) {
+      // one plane of fp16 pairs scaled so that the tensor's largest entry lands near 2^14
+      w[idx] = pack_f16x2(x.x * f16s, x.y * f16s);
+    } else {
+      // hi plane at word idx, lo plane split_plane words further, in this batch element
+      const uint32_t hi = pack_bf16x2(x.x, x.y);
+      const float hr = __uint_as_float(hi << 16), hiim = __uint_as_float(hi & 0xffff0000u);
+      w[idx] = hi;
+      w[a.split_plane + idx] = pack_bf16x2(x.x - hr, x.y - hiim);
+    }
+  }
+}
+
+// TB = 12: a full 2^12-element tile, 16 elements per thread, every load of the tile issued
+// before the first LDS write (16 x 8 bytes in flight per lane); TB = 0: any tile size up to 2^12
+// (small tensors), one element per thread and loop trip.  Tile index bits 0..7 come from the
+// thread, bits 8..t-1 from the trip counter; offsets are ORs of disjoint bit contributions, so the
+// thread's part is computed once and the trip's part is wave-uniform.
+template <int SPLIT, int TB>
 __global__ void __launch_bounds__(kPermThreads)
 permute_kernel(const float2* __restrict__ src, float2* __restrict__ dst, PermKernelArgs a) {
   extern __shared__ float2 tile[];
@@ -64,9 +94,8 @@ permute_kernel(const float2* __restrict__ src, float2* __restrict__ dst, PermKer
     sbase += bit << a.o_src[i];
     dbase += bit << a.o_dst[i];
   }
-  // Tile index bits 0..7 come from the thread, bits 8..t-1 from the loop counter; offsets are ORs
-  // of disjoint bit contributions, so the thread's part is computed once.
-  const int tid = threadIdx.x, t = a.t;
+  const int tid = threadIdx.x;
+  const int t = TB ? TB : a.t;
   const int lowb = t < 8 ? t : 8;
   const int tvol = 1 << t;
   const int iters = tvol >> lowb;
@@ -80,50 +109,83 @@ permute_kernel(const float2* __restrict__ src, float2* __restrict__ dst, PermKer
       w_lo |= (int64_t)bit << a.v_dst[i];
       u_lo |= bit << a.v_to_u[i];
     }
-  if (tid < tvol) {
-    for (int it = 0; it < iters; ++it) {
-      int64_t off = r_lo;
+  const float f16s = (SPLIT == 2 && a.f16_scale) ? ldexpf(1.f, 14 - renorm_exp(a.f16_scale)) : 1.f;
+  const float sre = a.scale, sim = a.scale * a.conj_sign;
+  if constexpr (TB == kPermMaxTile) {
+    constexpr int kIt = 1 << (kPermMaxTile - 8);
+    float2 v[kIt];
+    const float2* s0 = src + sbase + r_lo;
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      int64_t off = 0;
 #pragma unroll
       for (int i = 8; i < kPermMaxTile; ++i)
-        if (i < t && ((it >> (i - 8)) & 1)) off |= (int64_t)1 << a.u_src[i];
-      tile[lds_index(tid + (it << 8))] = src[sbase + off];
+        if ((it >> (i - 8)) & 1) off |= (int64_t)1 << a.u_src[i];
+      v[it] = s0[off];
     }
-  }
-  __syncthreads();
-  const float f16s = (a.split == 2 && a.f16_scale) ? ldexpf(1.f, 14 - renorm_exp(a.f16_scale)) : 1.f;
-  for (int it = 0; tid < tvol && it < iters; ++it) {
-    int u = u_lo;
-    int64_t off = w_lo;
 #pragma unroll
-    for (int i = 8; i < kPermMaxTile; ++i)
-      if (i < t && ((it >> (i - 8)) & 1)) {
-        u |= 1 << a.v_to_u[i];
-        off |= (int64_t)1 << a.v_dst[i];
+    for (int it = 0; it < kIt; ++it) tile[lds_index(tid + (it << 8))] = v[it];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      int u = u_lo;
+#pragma unroll
+      for (int i = 8; i < kPermMaxTile; ++i)
+        if ((it >> (i - 8)) & 1) u |= 1 << a.v_to_u[i];
+      v[it] = tile[lds_index(u)];
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      int64_t off = w_lo;
+#pragma unroll
+      for (int i = 8; i < kPermMaxTile; ++i)
+        if ((it >> (i - 8)) & 1) off |= (int64_t)1 << a.v_dst[i];
+      float2 x = v[it];
+      x.x *= sre;
+      x.y *= sim;
+      perm_store<SPLIT>(dst, a, dbase + off, x, f16s);
+    }
+  } else {
+    if (tid < tvol) {
+      for (int it = 0; it < iters; ++it) {
+        int64_t off = r_lo;
+#pragma unroll
+        for (int i = 8; i < kPermMaxTile; ++i)
+          if (i < t && ((it >> (i - 8)) & 1)) off |= (int64_t)1 << a.u_src[i];
+        tile[lds_index(tid + (it << 8))] = src[sbase + off];
       }
-    float2 x = tile[lds_index(u)];
-    x.x *= a.scale;
-    x.y *= a.scale * a.conj_sign;
-    if (a.split == 2) {
-      // one plane of fp16 pairs scaled so that the tensor's largest entry lands near 2^14
-      uint32_t* w = reinterpret_cast<uint32_t*>(dst);
-      int64_t idx = dbase + off;
-      if (a.split_ld)
-        idx = (idx >> a.split_kbits) * a.split_ld + (idx & (((int64_t)1 << a.split_kbits) - 1));
-      w[idx] = pack_f16x2(x.x * f16s, x.y * f16s);
-    } else if (a.split) {
-      // hi plane at word idx, lo plane split_plane words further, in this batch element
-      uint32_t* w = reinterpret_cast<uint32_t*>(dst);
-      int64_t idx = dbase + off;
-      if (a.split_ld)
-        idx = (idx >> a.split_kbits) * a.split_ld + (idx & (((int64_t)1 << a.split_kbits) - 1));
-      const uint32_t hi = pack_bf16x2(x.x, x.y);
-      const float hr = __uint_as_float(hi << 16), hiim = __uint_as_float(hi & 0xffff0000u);
-      w[idx] = hi;
-      w[a.split_plane + idx] = pack_bf16x2(x.x - hr, x.y - hiim);
-    } else {
-      dst[dbase + off] = x;
+    }
+    __syncthreads();
+    for (int it = 0; tid < tvol && it < iters; ++it) {
+      int u = u_lo;
+      int64_t off = w_lo;
+#pragma unroll
+      for (int i = 8; i < kPermMaxTile; ++i)
+        if (i < t && ((it >> (i - 8)) & 1)) {
+          u |= 1 << a.v_to_u[i];
+          off |= (int64_t)1 << a.v_dst[i];
+        }
+      float2 x = tile[lds_index(u)];
+      x.x *= sre;
+      x.y *= sim;
+      perm_store<SPLIT>(dst, a, dbase + off, x, f16s);
     }
   }
+}
+
+// The full-tile form pays for the FP16 form (12 bytes per element: on 2^30 elements 5.5 against
+// 5.25 TB/s for the loop); for complex64 and split-BF16 outputs (16 bytes per element) the loop is
+// 1-3% faster on the permutations measured, so those keep it.
+template <int SPLIT>
+static void launch_permute_split(hipStream_t st, dim3 grid, size_t lds, const float2* src, float2* dst,
+                                 const PermKernelArgs& a) {
+  if constexpr (SPLIT == 2) {
+    if (a.t == kPermMaxTile) {
+      hipLaunchKernelGGL((permute_kernel<SPLIT, kPermMaxTile>), grid, dim3(kPermThreads), lds, st, src, dst, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((permute_kernel<SPLIT, 0>), grid, dim3(kPermThreads), lds, st, src, dst, a);
 }
 
 hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const PermuteArgs& p) {
@@ -178,8 +240,13 @@ hipError_t launch_permute(hipStream_t st, const float2* src, float2* dst, const 
   const unsigned gx = (unsigned)std::min<int64_t>(tiles, 65536);
   const unsigned gy = (unsigned)(tiles / gx);
   const size_t lds = (size_t)((1 << t) + (1 << t) / 32 + 1) * sizeof(float2);
-  hipLaunchKernelGGL(permute_kernel, dim3(gx, gy, (unsigned)std::max(1, p.batch)), dim3(kPermThreads), lds, st,
-                     src, dst, a);
+  const dim3 grid(gx, gy, (unsigned)std::max(1, p.batch));
+  if (a.split == 2)
+    launch_permute_split<2>(st, grid, lds, src, dst, a);
+  else if (a.split)
+    launch_permute_split<1>(st, grid, lds, src, dst, a);
+  else
+    launch_permute_split<0>(st, grid, lds, src, dst, a);
   return hipGetLastError();
 }
 

@@ -330,7 +330,9 @@ def test_11x11_d24_scaled_product_circuit_full_shape(ctx, precision):
     bound = {"fp32": 1e-5, "bf16x3": len(plan["steps"]) * 2.0 ** -16, "fp16": 3e-2}[precision]
     got = Plan(ctx, circ, plan, precision).amplitudes(bits, s, s + 1)
     torch.cuda.synchronize()
-    assert rel_err(got.cpu().numpy()[0], ref) <= bound
+    err = rel_err(got.cpu().numpy()[0], ref)
+    _say(f"  rel err {err:.2e} (bound {bound:.1e})")
+    assert err <= bound
     if precision == "fp32":
         flat = Plan(ctx, circ, plan, precision, renorm=False).amplitudes(bits, s, s + 1)
         torch.cuda.synchronize()
