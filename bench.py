@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-subcheck", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip timing the GEMM kernel variants of the plans' shapes before the warmup")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip measuring the card's MFMA-loop and streaming-copy ceilings")
     ap.add_argument("--calib-copy", action="store_true",
                     help="launch one plain 1 GiB device copy first (HBM counter calibration)")
     ap.add_argument("--workload", default="7x7-d40", choices=["7x7-d40", "7x7-d32", "8x9-d24", "6x6-d24-grad", "11x11-d24", "vendor-gemm"],
@@ -49,6 +51,20 @@ def parse():
                          "amplitudes; 7x7-d32: whole 16-slice path sums in FP32 beside split-BF16; 11x11-d24: 121 qubits, a run of slices of the 64-slice region plan; vendor-gemm: the vendor real BF16 / FP32 GEMM on the same GPU (context for "
                          "the roofline: what the matrix cores sustain under the power limit)")
     return ap.parse_args()
+
+
+def measure_ceilings(ctx):
+    """What this card sustains, beside the nominal peaks: register-only MFMA loops (BF16, FP16,
+    FP32 instructions, about 0.2 s per launch so that the clock settles under the power limit) and
+    a streaming copy of 4 GiB (8 GiB read plus written per launch)."""
+    from paper_1905_00444_amd import time_ceiling
+    out = {"mfma_loop_tflops": {}, "unit_mfma": "TFLOP/s (real, dense)", "unit_copy": "TB/s (read + written)"}
+    for prec, trips in (("bf16x3", 100000), ("fp16", 100000), ("fp32", 60000)):
+        ms, flops = time_ceiling(ctx, "mfma", prec, trips, reps=3)
+        out["mfma_loop_tflops"]["bf16" if prec == "bf16x3" else prec] = flops / ms / 1e9
+    ms, nbytes = time_ceiling(ctx, "copy", size=8 << 30, reps=10)
+    out["copy_tbps"] = nbytes / ms / 1e9
+    return out
 
 
 def bench_8x9(args):
@@ -490,6 +506,11 @@ def main():
             torch.cuda.synchronize()
             print(f"bench: autotune {prec} {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
+    ceil = None
+    if not args.no_ceilings:
+        ceil = measure_ceilings(ctx)
+        print(f"bench: ceilings {ceil}", file=sys.stderr, flush=True)
+
     if args.calib_copy:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
@@ -589,6 +610,13 @@ def main():
                                   "achieved counts algorithmic complex flops 8*M*N*K",
                      "launches": bf["gemm_launches"], "avg_ms": gemm_avg_ms},
     }
+    if ceil:
+        mpeak = ceil["mfma_loop_tflops"]["bf16"] / 3.0
+        rec["roofline"]["measured_peak"] = mpeak
+        rec["roofline"]["frac_of_measured"] = achieved / mpeak
+        rec["roofline"]["measured_note"] = ("register-only loop of v_mfma_f32_16x16x32_bf16 on this card (no memory "
+                                            "traffic, pseudo-random operands) / 3 products")
+        rec["ceilings"] = ceil
     if args.whole_prefixes > 0:
         # whole amplitudes: every slice of the prefix that can be nonzero (the other 896 of the 1024
         # paths are identically zero for this circuit), split-BF16

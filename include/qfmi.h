@@ -319,6 +319,23 @@ qf_status qf_time_cgemm(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_
 qf_status qf_time_permute(qf_ctx* ctx, const void* src, void* dst, int nbits, const int32_t* perm,
                           int reps, float* ms);
 
+/* Measured ceilings of the card for rooflines: the paper reports its contractions against the
+ * GPU's peak (Sec. V-A); these two measurements give the rates that this card sustains, beside
+ * the nominal peaks.  kind QF_CEIL_COPY: a streaming copy of size / 2 bytes from the first half
+ * of the device buffer buf to its second half (size a positive multiple of 32 KiB; 16-byte
+ * accesses, 1 KiB contiguous per wave); *work = size (bytes read plus bytes written).
+ * kind QF_CEIL_MFMA: a register-only loop of the MFMA instruction of `precision` (QF_FP32:
+ * v_mfma_f32_16x16x4_f32, QF_BF16X3: v_mfma_f32_16x16x32_bf16, QF_FP16: v_mfma_f32_16x16x32_f16)
+ * on pseudo-random operands of magnitude 2^-2 .. 2^1, 32 independent accumulators per wave, two
+ * waves per SIMD, size = trips of the loop (>= 1); buf: 4 bytes or more of device memory, never
+ * written for these operands; *work = real flops of one launch.  One untimed launch, then `reps`
+ * launches timed with HIP events on the context's stream; *ms = average milliseconds per launch.
+ * Synchronises the stream.  Errors: QF_ERR_ARG (null pointers, unknown kind or precision,
+ * reps < 1, size out of range), QF_ERR_HIP. */
+enum { QF_CEIL_COPY = 0, QF_CEIL_MFMA = 1 };
+qf_status qf_time_ceiling(qf_ctx* ctx, int kind, int precision, void* buf, int64_t size, int reps, float* ms,
+                          double* work);
+
 /* Autotuning of the GEMM kernels that a plan launches.  Not in the paper, whose contractions
  * call the vendor library's default complex GEMM (Sec. III-E); here the kernel for each shape is
  * chosen by measurement.  For every distinct GEMM

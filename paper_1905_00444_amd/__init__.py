@@ -6,4 +6,4 @@ is its thin Python binding.  Build the library with `python -m paper_1905_00444_
 from .api import Context, Circuit, Plan, PRECISIONS, cgemm, permute, time_cgemm, time_permute  # noqa: F401
 from .api import profile_enable, profile_read, read_circuit_text  # noqa: F401
 from .api import split_bf16, split_f16, cgemm_presplit, time_cgemm_presplit  # noqa: F401
-from .api import autotune, tuned_variant, amplitudes  # noqa: F401
+from .api import autotune, tuned_variant, amplitudes, time_ceiling  # noqa: F401

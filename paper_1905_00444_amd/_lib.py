@@ -91,6 +91,8 @@ EXPORTS = {
                                 C.c_void_p, C.c_int, C.POINTER(C.c_float)]),
     "qf_time_permute": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_int,
                                   C.POINTER(C.c_float)]),
+    "qf_time_ceiling": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_int, C.POINTER(C.c_float),
+                                  C.POINTER(C.c_double)]),
     "qf_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "qf_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_char_p]),
     "qf_tuned_variant": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int64,

@@ -371,6 +371,24 @@ def time_permute(ctx: Context, src, dst, perm: Sequence[int], reps: int = 5) -> 
     return ms.value
 
 
+def time_ceiling(ctx: Context, kind: str, precision: str = "bf16x3", size: int = 0, buf=None, reps: int = 3):
+    """Measured ceiling of the card (qf_time_ceiling): kind "copy" streams size / 2 bytes of buf (a
+    device tensor of size bytes, allocated here if None) into its other half; kind "mfma" runs
+    `size` trips of the register-only MFMA loop of `precision`.  Returns (ms per launch, work of
+    one launch: bytes moved or real flops)."""
+    torch = _torch()
+    kinds = {"copy": 0, "mfma": 1}
+    if buf is None:
+        n = size if kind == "copy" else 4
+        with torch.cuda.stream(ctx.stream):
+            buf = torch.empty(n, dtype=torch.uint8, device=ctx.device)
+    ms = C.c_float()
+    work = C.c_double()
+    check(ctx.lib.qf_time_ceiling(ctx.h, kinds[kind], PRECISIONS[precision], C.c_void_p(buf.data_ptr()), int(size),
+                                  int(reps), C.byref(ms), C.byref(work)), ctx.h)
+    return ms.value, work.value
+
+
 def profile_enable(ctx: Context, on: bool = True) -> None:
     check(ctx.lib.qf_profile_enable(ctx.h, 1 if on else 0), ctx.h)
 

@@ -26,7 +26,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-Wno-unused-result",
 ]
-SOURCES = ["worldline.hip", "permute.hip", "cgemm.hip", "cgemm_presplit.hip", "cgemm_tall.hip", "runtime.cpp"]
+SOURCES = ["worldline.hip", "permute.hip", "cgemm.hip", "cgemm_presplit.hip", "cgemm_tall.hip", "ceiling.hip", "runtime.cpp"]
 
 
 def _compile(src: str) -> str:

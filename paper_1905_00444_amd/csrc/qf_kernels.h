@@ -94,6 +94,14 @@ hipError_t launch_seed_root(hipStream_t st, const double2* cot, int k, const int
 hipError_t launch_seed_root_batched(hipStream_t st, const double2* cot, int k, const int* pos, int G,
                                     const int32_t* chain_b, float2* env_root);
 
+// Measured ceilings (ceiling.hip): a register-only MFMA loop of `iters` trips over
+// ceiling_mfma_blocks() workgroups (flops of one launch: ceiling_mfma_flops), and a streaming copy
+// of `bytes` (a positive multiple of 16 KiB) from src to dst.
+int64_t ceiling_mfma_blocks();
+double ceiling_mfma_flops(int precision, int64_t iters);
+hipError_t launch_ceiling_mfma(hipStream_t st, int precision, float* sink, int64_t iters);
+hipError_t launch_stream_copy(hipStream_t st, const void* src, void* dst, int64_t bytes);
+
 hipError_t launch_zero(hipStream_t st, void* p, size_t bytes);
 
 // Per-leaf description of the bits fixed per chain (a chain is one bitstring x one slice).

@@ -1740,6 +1740,44 @@ qf_status qf_time_permute(qf_ctx* c, const void* src, void* dst, int nbits, cons
   return QF_OK;
 }
 
+qf_status qf_time_ceiling(qf_ctx* c, int kind, int precision, void* buf, int64_t size, int reps, float* ms,
+                          double* work) {
+  if (!c || !buf || !ms || !work || reps < 1) return fail(c, QF_ERR_ARG, "qf_time_ceiling: bad arguments");
+  if (kind == QF_CEIL_COPY) {
+    if (size <= 0 || size % (32 << 10) != 0)
+      return fail(c, QF_ERR_ARG, "qf_time_ceiling: copy size must be a positive multiple of 32 KiB");
+  } else if (kind == QF_CEIL_MFMA) {
+    if (size < 1) return fail(c, QF_ERR_ARG, "qf_time_ceiling: the MFMA loop needs at least one trip");
+    if (precision != QF_FP32 && precision != QF_BF16X3 && precision != QF_FP16)
+      return fail(c, QF_ERR_ARG, "qf_time_ceiling: unknown precision");
+  } else {
+    return fail(c, QF_ERR_ARG, "qf_time_ceiling: unknown kind");
+  }
+  auto launch = [&]() -> hipError_t {
+    if (kind == QF_CEIL_COPY) {
+      char* p = static_cast<char*>(buf);
+      return launch_stream_copy(c->stream, p, p + size / 2, size / 2);
+    }
+    return launch_ceiling_mfma(c->stream, precision, static_cast<float*>(buf), size);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(c, QF_ERR_HIP, hipGetErrorString(e));
+  *ms = t / reps;
+  *work = kind == QF_CEIL_COPY ? (double)size : ceiling_mfma_flops(precision, size);
+  return QF_OK;
+}
+
 qf_status qf_profile_enable(qf_ctx* c, int enable) {
   if (!c) return QF_ERR_ARG;
   c->profile = enable != 0;

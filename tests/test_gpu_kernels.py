@@ -414,3 +414,26 @@ def test_cgemm_presplit_f16_rejects_short_k(ctx):
     z = torch.zeros(256 * 16, dtype=torch.int32, device="cuda")
     with pytest.raises(RuntimeError):
         cgemm_presplit(ctx, z, z[:128 * 16], 256, 128, 16, precision="fp16")
+
+
+def test_ceiling_copy_and_mfma_loops(ctx):
+    """qf_time_ceiling: the streaming copy leaves the second half of the buffer equal to the first
+    and reports the bytes read plus written; each MFMA loop reports blocks x waves x trips x 32
+    MFMAs x the instruction's flops, at a rate below the instruction's nominal peak; sizes the copy
+    cannot take are rejected."""
+    import torch
+    from paper_1905_00444_amd import time_ceiling
+    _say("ceilings: copy and MFMA loops")
+    n = 1 << 20
+    buf = torch.randint(0, 256, (n,), dtype=torch.uint8, device=ctx.device)
+    torch.cuda.synchronize()
+    ms, work = time_ceiling(ctx, "copy", size=n, buf=buf, reps=2)
+    h = buf.cpu().numpy()
+    assert work == n and ms > 0
+    assert np.array_equal(h[: n // 2], h[n // 2:])
+    for prec, per, peak in (("bf16x3", 16384, 2516.6), ("fp16", 16384, 2516.6), ("fp32", 2048, 157.3)):
+        ms, fl = time_ceiling(ctx, "mfma", prec, 200, reps=2)
+        assert fl == 1024 * 8 * 200 * 32 * per
+        assert 0 < fl / ms / 1e9 < 1.05 * peak, prec
+    with pytest.raises(Exception):
+        time_ceiling(ctx, "copy", size=3 << 10, buf=buf)
