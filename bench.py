@@ -615,7 +615,9 @@ def main():
         rec["roofline"]["measured_peak"] = mpeak
         rec["roofline"]["frac_of_measured"] = achieved / mpeak
         rec["roofline"]["measured_note"] = ("register-only loop of v_mfma_f32_16x16x32_bf16 on this card (no memory "
-                                            "traffic, pseudo-random operands) / 3 products")
+                                            "traffic, pseudo-random operands) / 3 products; the sustained rate "
+                                            "depends on the operands through power, and the benchmark's operands "
+                                            "draw less than random ones, so this fraction can exceed 1")
         rec["ceilings"] = ceil
     if args.whole_prefixes > 0:
         # whole amplitudes: every slice of the prefix that can be nonzero (the other 896 of the 1024
