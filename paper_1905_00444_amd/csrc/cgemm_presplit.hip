@@ -96,37 +96,41 @@ __device__ __forceinline__ void ps_read(const char* st, int wr, int wc, int l16,
 }
 
 // The products of one K-tile for every accumulator.  Split-BF16: lo x hi, hi x lo, then hi x hi,
-// so the largest product is added last.  FP16: the first 16-complex half, then the second.
+// so the largest product is added last.  FP16: the first 16-complex half, then the second.  The
+// B fragment is the outer operand (one B fragment for 8 consecutive MFMAs while the A fragment
+// changes): under the card's power limit a register-only MFMA loop sustains about 4% more when
+// the B operand stays fixed between consecutive instructions than when it changes every time.
+// Each accumulator still receives its products in the order above.
 template <int PREC>
 __device__ __forceinline__ void ps_multiply(const u4 (&ah)[kPsWI], const u4 (&al)[kPsWI], const u4 (&bh)[kPsWJ],
                                             const u4 (&bl)[kPsWJ], f4 (&acc)[kPsWI][kPsWJ]) {
   if constexpr (PREC == P_FP16) {
 #pragma unroll
-    for (int i = 0; i < kPsWI; ++i) {
+    for (int j = 0; j < kPsWJ; ++j) {
 #pragma unroll
-      for (int j = 0; j < kPsWJ; ++j)
+      for (int i = 0; i < kPsWI; ++i)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, ah[i]), __builtin_bit_cast(h8, bh[j]),
                                                            acc[i][j], 0, 0, 0);
 #pragma unroll
-      for (int j = 0; j < kPsWJ; ++j)
+      for (int i = 0; i < kPsWI; ++i)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, al[i]), __builtin_bit_cast(h8, bl[j]),
                                                            acc[i][j], 0, 0, 0);
     }
     return;
   }
 #pragma unroll
-  for (int i = 0; i < kPsWI; ++i) {
-    const bf8 a_h = __builtin_bit_cast(bf8, ah[i]);
-    const bf8 a_l = __builtin_bit_cast(bf8, al[i]);
+  for (int j = 0; j < kPsWJ; ++j) {
+    const bf8 b_h = __builtin_bit_cast(bf8, bh[j]);
+    const bf8 b_l = __builtin_bit_cast(bf8, bl[j]);
 #pragma unroll
-    for (int j = 0; j < kPsWJ; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+    for (int i = 0; i < kPsWI; ++i)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, al[i]), b_h, acc[i][j], 0, 0, 0);
 #pragma unroll
-    for (int j = 0; j < kPsWJ; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, __builtin_bit_cast(bf8, bl[j]), acc[i][j], 0, 0, 0);
+    for (int i = 0; i < kPsWI; ++i)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), b_l, acc[i][j], 0, 0, 0);
 #pragma unroll
-    for (int j = 0; j < kPsWJ; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+    for (int i = 0; i < kPsWI; ++i)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[i]), b_h, acc[i][j], 0, 0, 0);
   }
 }
 
