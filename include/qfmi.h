@@ -157,11 +157,12 @@ qf_status qf_ctx_create(int device, void* hip_stream, void* workspace, size_t ws
  * housekeeping, no counterpart in the paper).  Errors: QF_ERR_ARG. */
 qf_status qf_ctx_set_workspace(qf_ctx* ctx, void* workspace, size_t ws_bytes);
 qf_status qf_ctx_set_stream(qf_ctx* ctx, void* hip_stream);
-/* Destroys the context.  Circuits and plans still alive are detached, not freed: destroy them
- * as usual later; every other call on them then fails with QF_ERR_ARG.  Destroying a circuit
- * likewise detaches the plans built on it. */
+/* Destroys the context (housekeeping, no counterpart in the paper).  Circuits and plans still
+ * alive are detached, not freed: destroy them as usual later; every other call on them then
+ * fails with QF_ERR_ARG.  Destroying a circuit likewise detaches the plans built on it. */
 void qf_ctx_destroy(qf_ctx* ctx);
-/* Text of the context's last error (owned by the context, valid until its next call). */
+/* Text of the context's last error (owned by the context, valid until its next call;
+ * housekeeping, no counterpart in the paper). */
 const char* qf_last_error(const qf_ctx* ctx);
 
 /* Circuit on a rows x cols grid; present[r*cols+c] != 0 marks a live site (NULL = all).
@@ -177,6 +178,7 @@ qf_status qf_circuit_create(qf_ctx* ctx, int rows, int cols, const uint8_t* pres
  * with other gate tensors (Sec. II), for finite differences and autograd; world-lines are
  * rebuilt on the next call.  Errors: QF_ERR_ARG. */
 qf_status qf_circuit_set_values(qf_circuit* circ, const float* values);
+/* Frees a circuit; plans built on it are detached (housekeeping, no counterpart in the paper). */
 void qf_circuit_destroy(qf_circuit* circ);
 
 /* Validate a plan against a circuit and lay out its workspace (host only).  The plan is the
@@ -199,14 +201,16 @@ qf_status qf_plan_info_get(const qf_plan* plan, qf_plan_info* out);
  * batched plans with cuts run the steps that depend on no cut once per launch group of G
  * slices (host only).  Errors: QF_ERR_ARG (bad range). */
 qf_status qf_plan_flops(const qf_plan* plan, int64_t s_begin, int64_t s_end, double* flops);
-/* Graph execution of a batched plan created with QF_PLAN_GRAPH (host only): *launches = the
- * hipGraphLaunch calls made for this plan so far (one per qf_amplitudes call), *nodes = the nodes
- * of the graph currently captured (0 before the first call).  Errors: QF_ERR_ARG (null pointer),
- * QF_ERR_HIP. */
+/* Graph execution of a batched plan created with QF_PLAN_GRAPH (host only; the paper's runtime
+ * pipelines its contractions asynchronously on streams, Sec. III-E, where a call here replays one
+ * captured graph): *launches = the hipGraphLaunch calls made for this plan so far (one per
+ * qf_amplitudes call), *nodes = the nodes of the graph currently captured (0 before the first
+ * call).  Errors: QF_ERR_ARG (null pointer), QF_ERR_HIP. */
 qf_status qf_plan_graph_info(const qf_plan* plan, int64_t* launches, int64_t* nodes);
 /* Description of step i (0 <= i < n_steps) of a laid-out plan: its TTGT roles and shapes
  * (Sec. III-E) (host only).  Errors: QF_ERR_ARG. */
 qf_status qf_plan_step_info(const qf_plan* plan, int i, qf_step_info* out);
+/* Frees a plan and its captured graph (housekeeping, no counterpart in the paper). */
 void qf_plan_destroy(qf_plan* plan);
 
 /* Amplitudes for n_batch bitstrings over slices [s_begin, s_end) (paper Sec. III-A: the
@@ -272,7 +276,8 @@ qf_status qf_cgemm(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, 
                    const void* B, void* C, int64_t batch, int64_t stride_a, int64_t stride_b,
                    int64_t stride_c);
 
-/* Same as qf_cgemm with an explicit kernel variant (comparison runs and tests):
+/* Same as qf_cgemm (the "G" of Sec. III-E) with an explicit kernel variant (comparison runs and
+ * tests):
  *   0 auto, 1 tiled 128 x 64, 2 tiled 64 x 32, 3 tiled 32 x 32, 4 large 256 x 128, 5 skinny
  *   (SIMT FP32, B in LDS), 6 split-K reduction per output, 7 one thread per output, 8 tall
  *   (M large, powers of two with 8 <= N <= 64 and 16 <= K <= 64: B in LDS, A streamed).
@@ -353,7 +358,8 @@ qf_status qf_time_ceiling(qf_ctx* ctx, int kind, int precision, void* buf, int64
  * smaller than the plan needs), QF_ERR_HIP, QF_ERR_ARG with text if the file cannot be written. */
 qf_status qf_autotune(qf_ctx* ctx, const qf_plan* plan, const char* cache_path);
 
-/* Variant installed for a GEMM shape on this context (0: none, the shape heuristic applies;
+/* Variant installed for a GEMM shape on this context by qf_autotune (not in the paper, see
+ * there; 0: none, the shape heuristic applies;
  * 1..7: see qf_autotune's JSON names tiled4x4, tiled2x2, tiled1x2, large, skinny, splitk, simt). */
 qf_status qf_tuned_variant(const qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, int64_t batch,
                            int* variant);
