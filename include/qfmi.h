@@ -138,6 +138,9 @@ typedef struct {
                                        only fixes bits or splits into bfloat16 planes) */
   int32_t presplit;           /* split-BF16 GEMM on operands split by their permutes */
   int32_t persistent;         /* the result is kept across slices (no cut bit it depends on changes) */
+  int32_t out_q, out_nh;      /* output order: 0, 0 for C[M][N]; else the GEMM writes element (m, n)
+                                 with the top out_nh bits of n above the low out_q bits of m, so
+                                 that the consuming step reads the result in place */
   double flops;               /* 8 * 2^(m+n+k) */
 } qf_step_info;
 

@@ -84,7 +84,7 @@ __device__ __forceinline__ void scales_for(const Renorm& rn, const uint32_t* ama
 constexpr int kReduceLanes = 32;
 
 __global__ void __launch_bounds__(256)
-cgemm_split_reduce(const float2* __restrict__ P, int split, int64_t batch, int64_t MN, int64_t sc,
+cgemm_split_reduce(const float2* __restrict__ P, int split, int64_t batch, int64_t MN, int64_t N, int64_t sc,
                    float2* __restrict__ C, Renorm rn) {
   float sa_, sb_, unscale;
   renorm_begin<P_FP32>(rn, nullptr, nullptr, sa_, sb_, unscale);
@@ -109,8 +109,8 @@ cgemm_split_reduce(const float2* __restrict__ P, int split, int64_t batch, int64
     }
     if (t == 0) {
       const float2 o = make_float2(re * unscale, im * unscale);
-      const int64_t b = i / MN;
-      C[b * sc + (i - b * MN)] = o;
+      const int64_t b = i / MN, e = i - b * MN, m = e / N;
+      C[b * sc + c_index(rn, m, e - m * N, N)] = o;
       mx = fmaxf(mx, cmax(o));
     }
   }
@@ -317,8 +317,8 @@ cgemm_mfma(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
       float2 o0, o1;
       if (q) { o0 = make_float2(r0, v[2]); o1 = make_float2(r1, v[3]); }
       else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
-      C[row * N + col] = o0;
-      C[(row + 1) * N + col] = o1;
+      C[partial ? row * N + col : c_index(rn, row, col, N)] = o0;
+      C[partial ? (row + 1) * N + col : c_index(rn, row + 1, col, N)] = o1;
       mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
     }
   if (rn.c && !partial) record_amax(rn.c, mx);
@@ -505,8 +505,8 @@ cgemm_v2(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const fl
       float2 o0, o1;
       if (q) { o0 = make_float2(r0, v[2]); o1 = make_float2(r1, v[3]); }
       else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
-      C[row * N + col] = o0;
-      C[(row + 1) * N + col] = o1;
+      C[partial ? row * N + col : c_index(rn, row, col, N)] = o0;
+      C[partial ? (row + 1) * N + col : c_index(rn, row + 1, col, N)] = o1;
       mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
     }
   if (rn.c && !partial) record_amax(rn.c, mx);
@@ -630,8 +630,8 @@ cgemm_v2f32(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const
       float2 o0, o1;
       if (q) { o0 = make_float2(r0, v[2]); o1 = make_float2(r1, v[3]); }
       else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
-      C[row * N + col] = o0;
-      C[(row + 1) * N + col] = o1;
+      C[partial ? row * N + col : c_index(rn, row, col, N)] = o0;
+      C[partial ? (row + 1) * N + col : c_index(rn, row + 1, col, N)] = o1;
       mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
     }
   if (rn.c && !partial) record_amax(rn.c, mx);
@@ -663,7 +663,7 @@ cgemm_simt(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, const 
       ci = fmaf(x.y, y.x, ci);
     }
     const float2 o = make_float2(cr * unscale, ci * unscale);
-    C[m * N + n] = o;
+    C[c_index(rn, m, n, N)] = o;
     mx = fmaxf(mx, cmax(o));
   }
   if (rn.c) record_amax(rn.c, mx);
@@ -713,11 +713,10 @@ cgemm_skinny(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, cons
         ci[t] = fmaf(x.y, y.x, ci[t]);
       }
     }
-    float2* out = C + m * N + g;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const float2 v = make_float2(cr[t] * unscale, ci[t] * unscale);
-      out[t * Q] = v;
+      C[c_index(rn, m, g + t * Q, N)] = v;
       mx = fmaxf(mx, cmax(v));
     }
   }
@@ -755,7 +754,7 @@ cgemm_splitk(int64_t M, int64_t N, int64_t K, const float2* __restrict__ A, cons
   if (threadIdx.x == 0) {
     const float r = (red[0][0] + red[0][1] + red[0][2] + red[0][3]) * unscale;
     const float i = (red[1][0] + red[1][1] + red[1][2] + red[1][3]) * unscale;
-    C[batch * sc + out] = make_float2(r, i);
+    C[batch * sc + c_index(rn, m, n, N)] = make_float2(r, i);
     if (rn.c) atomicMax(&rn.c->amax, __float_as_uint(fmaxf(fabsf(r), fabsf(i))));
   }
 }
@@ -909,7 +908,7 @@ hipError_t launch_cgemm_ex(hipStream_t st, int precision, int64_t M, int64_t N, 
   const int64_t total = batch * M * N;
   const int64_t per_block = 256 / kReduceLanes;
   const unsigned blocks = (unsigned)std::min<int64_t>((total + per_block - 1) / per_block, 16384);
-  hipLaunchKernelGGL(cgemm_split_reduce, dim3(blocks), dim3(256), 0, st, scratch, split, batch, M * N, sc, C, rn);
+  hipLaunchKernelGGL(cgemm_split_reduce, dim3(blocks), dim3(256), 0, st, scratch, split, batch, M * N, N, sc, C, rn);
   return hipGetLastError();
 }
 

@@ -26,6 +26,15 @@ __device__ __forceinline__ uint32_t pack_f16x2(float re, float im) {
   return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
 }
 
+// Index of element (m, n) of a C[M][N] result under the epilogue's output map (Renorm::om_*):
+// m * N + n, or with om_nh > 0 the top om_nh bits of n placed above the low om_q bits of m.
+__device__ __forceinline__ int64_t c_index(const Renorm& rn, int64_t m, int64_t n, int64_t N) {
+  if (rn.om_nh == 0) return m * N + n;
+  const int q = rn.om_q, nl = rn.om_nl, nh = rn.om_nh;
+  const int64_t mlo = m & (((int64_t)1 << q) - 1), nlo = n & (((int64_t)1 << nl) - 1);
+  return ((((m >> q) << (nh + q)) | ((n >> nl) << q) | mlo) << nl) | nlo;
+}
+
 // Scale exponent that brings max|x| to about 2^14 (FP16 max is 65504 ~ 2^16).
 __device__ __forceinline__ int fp16_shift(const uint32_t* amax) {
   if (!amax) return 0;

@@ -176,8 +176,8 @@ cgemm_tall(int64_t M, const float2* __restrict__ A, const float2* __restrict__ B
         float2 o0, o1;
         if (q) { o0 = make_float2(r0, v[2]); o1 = make_float2(r1, v[3]); }
         else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
-        C[row * N + col] = o0;
-        C[(row + 1) * N + col] = o1;
+        C[c_index(rn, row, col, N)] = o0;
+        C[c_index(rn, row + 1, col, N)] = o1;
         mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
       }
   }

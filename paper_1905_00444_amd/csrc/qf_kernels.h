@@ -21,6 +21,11 @@ struct Renorm {
   const NodeScale* a = nullptr;
   const NodeScale* b = nullptr;
   NodeScale* c = nullptr;
+  // Output map of the epilogue: with om_nh > 0, C[m][n] goes to index
+  // ((m >> om_q) << (om_nh + om_q) | (n >> om_nl) << om_q | (m mod 2^om_q)) << om_nl | (n mod 2^om_nl),
+  // i.e. the top om_nh bits of n sit above the low om_q bits of m (om_nl = log2 N - om_nh);
+  // om_nh = 0: C[m][n] at m * N + n.
+  int om_q = 0, om_nh = 0, om_nl = 0;
 };
 
 // One instruction of a qubit's world-line program.

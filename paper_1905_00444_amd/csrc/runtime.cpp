@@ -115,6 +115,7 @@ struct Step {
   int m_bits = 0, n_bits = 0, k_bits = 0;
   bool presplit = false;  // split-BF16 GEMM on operands split by their permutes
   bool fold = false;      // group hoisting, B shared by the group's chains: one GEMM of G M rows
+  int om_q = 0, om_nh = 0;  // output order [A free high][B free top om_nh][A free low om_q][B free rest]
   double flops = 0.0;
   size_t out = 0;         // arena offset of the result
 };
@@ -197,6 +198,54 @@ static qf_status fail(qf_ctx* ctx, qf_status st, const std::string& msg) {
 
 static qf_status hip_fail(qf_ctx* ctx, hipError_t e, const char* what) {
   return fail(ctx, QF_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Order of a step's result.  Each label goes by the step that contracts it, the latest on top
+// (open output legs highest), so that the consuming step finds its contracted labels trailing
+// and reads the result in place.  The free labels of an operand that is read in place keep their
+// order; those of a permuted operand are sorted.  The GEMM writes C[m][n] at m * N + n, or with
+// its epilogue's output map at [A free high][top om_nh bits of n][low om_q bits of m][rest of n];
+// the sorted order is taken when it has that form and the runs of n's low bits stay at least
+// 8 elements (64 bytes) long, else the plain [A free][B free] of the sorted operand orders.
+static void order_output(const std::vector<int>& ctime, bool x_fixed, bool y_fixed, std::vector<int>& xf,
+                         std::vector<int>& yf, std::vector<int>& out, int& om_q, int& om_nh) {
+  auto later = [&](int a, int b) { return ctime[a] > ctime[b]; };
+  if (!x_fixed) std::stable_sort(xf.begin(), xf.end(), later);
+  if (!y_fixed) std::stable_sort(yf.begin(), yf.end(), later);
+  // merge by contraction step (ties keep the current run)
+  std::vector<std::pair<int, int>> runs;  // (side 0 = x / 1 = y, length), most significant first
+  size_t i = 0, j = 0;
+  int side = -1;
+  while (i < xf.size() || j < yf.size()) {
+    int take;
+    if (i == xf.size()) take = 1;
+    else if (j == yf.size()) take = 0;
+    else if (ctime[xf[i]] != ctime[yf[j]]) take = ctime[xf[i]] > ctime[yf[j]] ? 0 : 1;
+    else take = side == 1 ? 1 : 0;
+    if (take == 0) ++i;
+    else ++j;
+    if (take != side) runs.push_back({take, 0});
+    runs.back().second++;
+    side = take;
+  }
+  om_q = om_nh = 0;
+  out = xf;
+  out.insert(out.end(), yf.begin(), yf.end());
+  // realisable: the runs read x?, y, x, y? (at most one y run above an x run)
+  size_t r = 0;
+  int xa = 0, yh = 0, xb = 0, yl = 0;
+  if (r < runs.size() && runs[r].first == 0) xa = runs[r++].second;
+  if (r < runs.size() && runs[r].first == 1) yh = runs[r++].second;
+  if (r < runs.size() && runs[r].first == 0) xb = runs[r++].second;
+  if (r < runs.size() && runs[r].first == 1) yl = runs[r++].second;
+  if (r != runs.size() || xb == 0 || yh == 0) return;  // plain order, or not of the map's form
+  if (yl < 3) return;                                  // runs of n's low bits too short
+  out.assign(xf.begin(), xf.begin() + xa);
+  out.insert(out.end(), yf.begin(), yf.begin() + yh);
+  out.insert(out.end(), xf.begin() + xa, xf.end());
+  out.insert(out.end(), yf.begin() + yh, yf.end());
+  om_q = xb;
+  om_nh = yh;
 }
 
 #define QF_HIP(ctx, expr)                                   \
@@ -543,6 +592,12 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
                     (nd.dep_bits != cons.dep_bits || nd.dep_cuts != cons.dep_cuts);
   }
 
+  // ---- the step that contracts each label (labels never contracted, open output legs: n_steps)
+  std::vector<int> ctime((size_t)XBASE + n, (int)p->steps.size());
+  for (int i = 0; i < (int)p->steps.size(); ++i)
+    for (int lab : p->nodes[p->steps[i].l].labels)
+      if (contains(p->nodes[p->steps[i].r].labels, lab)) ctime[lab] = i;
+
   // ---- TTGT roles and layouts
   // batched forward plans with cuts run the cut-independent steps once per launch group (group
   // hoisting, below); a step that combines such a shared operand with a per-chain one takes the
@@ -575,6 +630,13 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     for (int lab : Y->labels) if (!contains(K, lab)) ywant.push_back(lab);
     out_node.labels = xwant;
     out_node.labels.insert(out_node.labels.end(), ywant.begin(), ywant.end());
+    if (!p->backward) {
+      // an intermediate whose contracted labels already trail in korder's order is read in place
+      auto in_place = [&](const Node* nd) {
+        return !nd->leaf && std::equal(nd->labels.end() - K.size(), nd->labels.end(), korder.begin());
+      };
+      order_output(ctime, in_place(X), in_place(Y), xwant, ywant, out_node.labels, st.om_q, st.om_nh);
+    }
     xwant.insert(xwant.end(), korder.begin(), korder.end());
     ywant.insert(ywant.end(), korder.begin(), korder.end());
     auto setup = [&](Operand& op, int id, const Node* nd, const std::vector<int>& want) {
@@ -827,6 +889,8 @@ qf_status qf_plan_step_info(const qf_plan* p, int i, qf_step_info* out) {
   out->b_reordered = st.B.permute && !order_preserving(st.B.perm);
   out->presplit = st.presplit;
   out->persistent = p->nodes[p->n + i].persistent;
+  out->out_q = st.om_q;
+  out->out_nh = st.om_nh;
   out->flops = st.flops;
   return QF_OK;
 }
@@ -967,8 +1031,11 @@ static qf_status run_operand(qf_plan* p, const Operand& op, const uint8_t* bits_
 // Renormalisation slots of step i's operands and result (all null when the plan stores true scales).
 static Renorm step_renorm(qf_plan* p, size_t i) {
   Renorm r;
-  if (!p->renorm) return r;
   const Step& st = p->steps[i];
+  r.om_q = st.om_q;
+  r.om_nh = st.om_nh;
+  r.om_nl = st.n_bits - st.om_nh;
+  if (!p->renorm) return r;
   r.a = node_scale(p, st.A.node);
   r.b = node_scale(p, st.B.node);
   r.c = node_scale(p, p->n + (int)i);

@@ -304,3 +304,36 @@ def test_batched_plans_with_cuts_run_cut_independent_steps_once_per_group():
             assert f1.value == pytest.approx(per_slice)
             assert (f.value - per_slice) / 255 < 0.01 * per_slice
     assert flops[256] < flops[16] < 256 * inf.flops_per_slice
+
+
+def test_output_order_lets_the_next_step_read_in_place():
+    """The layout pass orders each result by the step that contracts its labels, lifting the top
+    bits of N above the low bits of M where that order needs it: for the 70-qubit hand plan all but
+    a few of the large operands are then read in place, and every output map keeps runs of at
+    least 8 elements of N's low bits and stays within the step's bits."""
+    from workloads.plans import plan_8x9, C5_REMOVED
+    lib, ctx = _host_ctx()
+    circ = generate(8, 9, 24, 0, C5_REMOVED)
+    plan, _ = plan_8x9(circ)
+    st, ch = _circuit(lib, ctx, circ)
+    assert st == 0
+    st, ph = _plan(lib, ctx, ch, plan, precision=1)
+    assert st == 0
+    info = _lib.qf_plan_info()
+    assert lib.qf_plan_info_get(ph, C.byref(info)) == 0
+    big = permuted = mapped = 0
+    for i in range(info.n_steps):
+        si = _lib.qf_step_info()
+        assert lib.qf_plan_step_info(ph, i, C.byref(si)) == 0
+        if si.out_nh:
+            mapped += 1
+            assert 0 < si.out_q <= si.m_bits and si.n_bits - si.out_nh >= 3
+        for perm, bits in ((si.a_permuted, si.m_bits + si.k_bits), (si.b_permuted, si.n_bits + si.k_bits)):
+            if bits >= 24:
+                big += 1
+                permuted += perm
+    assert big == 50 and permuted <= 10 and mapped >= 20
+    assert info.permute_bytes < 2e10
+    lib.qf_plan_destroy(ph)
+    lib.qf_circuit_destroy(ch)
+    lib.qf_ctx_destroy(ctx)
