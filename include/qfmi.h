@@ -141,6 +141,8 @@ typedef struct {
   int32_t out_q, out_nh;      /* output order: 0, 0 for C[M][N]; else the GEMM writes element (m, n)
                                  with the top out_nh bits of n above the low out_q bits of m, so
                                  that the consuming step reads the result in place */
+  int32_t out_split;          /* the result is written as the split-BF16 operand of its consumer
+                                 (two bfloat16 planes, the consumer's row pitch), not complex64 */
   double flops;               /* 8 * 2^(m+n+k) */
 } qf_step_info;
 

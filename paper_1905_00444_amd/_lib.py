@@ -51,7 +51,8 @@ class qf_step_info(C.Structure):
                 ("m_bits", C.c_int32), ("n_bits", C.c_int32), ("k_bits", C.c_int32),
                 ("a_permuted", C.c_int32), ("b_permuted", C.c_int32), ("a_reordered", C.c_int32),
                 ("b_reordered", C.c_int32), ("presplit", C.c_int32), ("persistent", C.c_int32),
-                ("out_q", C.c_int32), ("out_nh", C.c_int32), ("flops", C.c_double)]
+                ("out_q", C.c_int32), ("out_nh", C.c_int32), ("out_split", C.c_int32),
+                ("flops", C.c_double)]
 
 
 EXPORTS = {

@@ -35,6 +35,20 @@ __device__ __forceinline__ int64_t c_index(const Renorm& rn, int64_t m, int64_t 
   return ((((m >> q) << (nh + q)) | ((n >> nl) << q) | mlo) << nl) | nlo;
 }
 
+// Store of result element (m, n): complex64 at c_index, or its split-BF16 planes (Renorm::so_*).
+__device__ __forceinline__ void store_c(float2* C, const Renorm& rn, int64_t m, int64_t n, int64_t N, float2 o) {
+  const int64_t j = c_index(rn, m, n, N);
+  if (rn.so_ld == 0) {
+    C[j] = o;
+    return;
+  }
+  uint32_t* w = reinterpret_cast<uint32_t*>(C);
+  const int64_t idx = (j >> rn.so_kbits) * rn.so_ld + (j & (((int64_t)1 << rn.so_kbits) - 1));
+  const uint32_t hi = pack_bf16x2(o.x, o.y);
+  w[idx] = hi;
+  w[rn.so_plane + idx] = pack_bf16x2(o.x - bf16_lo_to_f32(hi), o.y - bf16_hi_to_f32(hi));
+}
+
 // Scale exponent that brings max|x| to about 2^14 (FP16 max is 65504 ~ 2^16).
 __device__ __forceinline__ int fp16_shift(const uint32_t* amax) {
   if (!amax) return 0;

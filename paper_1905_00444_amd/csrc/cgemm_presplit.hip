@@ -246,8 +246,8 @@ cgemm_pingpong_presplit(int64_t M, int64_t N, int64_t K, const uint32_t* __restr
       float2 o0, o1;
       if (q) { o0 = make_float2(r0, v[2]); o1 = make_float2(r1, v[3]); }
       else { o0 = make_float2(v[0], r0); o1 = make_float2(v[1], r1); }
-      C[c_index(rn, row, col, N)] = o0;
-      C[c_index(rn, row + 1, col, N)] = o1;
+      store_c(C, rn, row, col, N, o0);
+      store_c(C, rn, row + 1, col, N, o1);
       mx = fmaxf(mx, fmaxf(cmax(o0), cmax(o1)));
     }
   if (rn.c) record_amax(rn.c, mx);

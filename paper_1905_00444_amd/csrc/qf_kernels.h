@@ -26,6 +26,12 @@ struct Renorm {
   // i.e. the top om_nh bits of n sit above the low om_q bits of m (om_nl = log2 N - om_nh);
   // om_nh = 0: C[m][n] at m * N + n.
   int om_q = 0, om_nh = 0, om_nl = 0;
+  // Split output (pre-split kernel, split-BF16): with so_ld > 0 the result goes out as the split
+  // operand of its consumer instead of complex64: element j of the (mapped) order at word
+  // (j >> so_kbits) * so_ld + (j mod 2^so_kbits) of a plane of bf16 hi pairs, its lo pair so_plane
+  // words further (hi = bf16(x), lo = bf16(x - hi), as the splitting permute writes them).
+  int so_kbits = 0;
+  int64_t so_ld = 0, so_plane = 0;
 };
 
 // One instruction of a qubit's world-line program.

@@ -116,9 +116,20 @@ struct Step {
   bool presplit = false;  // split-BF16 GEMM on operands split by their permutes
   bool fold = false;      // group hoisting, B shared by the group's chains: one GEMM of G M rows
   int om_q = 0, om_nh = 0;  // output order [A free high][B free top om_nh][A free low om_q][B free rest]
+  bool split_out = false;  // the result is written as its pre-split consumer's split-BF16 operand
+  int so_kbits = 0;        // ... with that operand's K bits and row pitch (words)
+  int64_t so_ld = 0;
   double flops = 0.0;
   size_t out = 0;         // arena offset of the result
 };
+
+// Complex64-sized elements (8 bytes) of one chain's copy of step st's result: dense, or the two
+// split planes of its consumer's operand with padded rows.
+static size_t result_elems(const Step& st) {
+  const int b = st.m_bits + st.n_bits;
+  if (!st.split_out) return (size_t)1 << b;
+  return ((size_t)1 << (b - st.so_kbits)) * (size_t)st.so_ld;
+}
 
 struct Buf {
   size_t bytes;
@@ -710,6 +721,27 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     }
   }
 
+  // ---- split output: a pre-split step whose split-BF16 operand is an intermediate read in place
+  // (its order needs no permute; only the split did) takes it straight from the producing step,
+  // when that step runs on the pre-split kernel too, which then writes the operand's two planes
+  // instead of complex64
+  if (!p->backward && p->precision == QF_BF16X3) {
+    for (Step& st : p->steps) {
+      if (!st.presplit) continue;
+      for (Operand* op : {&st.A, &st.B}) {
+        const Node& nd = p->nodes[op->node];
+        if (nd.leaf || !is_identity(op->perm)) continue;
+        Step& prod = p->steps[op->node - n];
+        if (!prod.presplit || prod.split_out) continue;
+        prod.split_out = true;
+        prod.so_kbits = op->kbits;
+        prod.so_ld = split_ld(*op);
+        op->permute = false;
+        p->permute_bytes -= 16.0 * std::ldexp(1.0, op->nbits);
+      }
+    }
+  }
+
   // ---- arena
   size_t cur = kCtxScratch;
   p->off_gates = cur;
@@ -725,8 +757,8 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   for (int i = 0; i < S; ++i) {
     Node& nd = p->nodes[n + i];
     const size_t G = (size_t)step_batch(p.get(), i);
-    const size_t bytes = align_up(G * (sizeof(float2) << nd.labels.size()));
     Step& st = p->steps[i];
+    const size_t bytes = align_up(G * sizeof(float2) * result_elems(st));
     const size_t GA = (size_t)operand_batch(p.get(), st.A), GB = (size_t)operand_batch(p.get(), st.B);
     if (p->backward) {
       // every forward tensor is kept for the reverse sweep, next to its environment
@@ -891,6 +923,7 @@ qf_status qf_plan_step_info(const qf_plan* p, int i, qf_step_info* out) {
   out->persistent = p->nodes[p->n + i].persistent;
   out->out_q = st.om_q;
   out->out_nh = st.om_nh;
+  out->out_split = st.split_out;
   out->flops = st.flops;
   return QF_OK;
 }
@@ -1035,6 +1068,11 @@ static Renorm step_renorm(qf_plan* p, size_t i) {
   r.om_q = st.om_q;
   r.om_nh = st.om_nh;
   r.om_nl = st.n_bits - st.om_nh;
+  if (st.split_out) {
+    r.so_kbits = st.so_kbits;
+    r.so_ld = st.so_ld;
+    r.so_plane = ((int64_t)1 << (st.m_bits + st.n_bits - st.so_kbits)) * st.so_ld;
+  }
   if (!p->renorm) return r;
   r.a = node_scale(p, st.A.node);
   r.b = node_scale(p, st.B.node);
@@ -1100,7 +1138,7 @@ static void trace_step(qf_plan* p, size_t i, const float2* A, const float2* B, i
   const int64_t M = (int64_t)1 << st.m_bits, N = (int64_t)1 << st.n_bits, K = (int64_t)1 << st.k_bits;
   const float ma = st.presplit ? -2.f : trace_amax(c, A, M * K);
   const float mb = st.presplit ? -2.f : trace_amax(c, B, N * K);
-  const float mc = trace_amax(c, wsp(c, p->nodes[p->n + i].offset), M * N);
+  const float mc = st.split_out ? -2.f : trace_amax(c, wsp(c, p->nodes[p->n + i].offset), M * N);
   std::fprintf(stderr, "qfmi trace: slice %lld step %zu (%d,%d) M=2^%d N=2^%d K=2^%d amax A %.3e B %.3e C %.3e\n",
                (long long)s, i, st.l, st.r, st.m_bits, st.n_bits, st.k_bits, ma, mb, mc);
 }
@@ -1126,8 +1164,8 @@ static qf_status run_step(qf_plan* p, size_t i, const uint8_t* row, int64_t s) {
   const Renorm rn = step_renorm(p, i);
   if (st.presplit) {
     const int64_t lda = split_ld(st.A), ldb = split_ld(st.B);
-    QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, 1, M * lda, N * ldb, M * N, rn, lda, ldb,
-                                    p->precision));
+    QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, 1, M * lda, N * ldb, (int64_t)result_elems(st), rn,
+                                    lda, ldb, p->precision));
   } else {
     e = plan_gemm(p, M, N, K, A, B, C, 1, rn);
     if (e != QF_OK) return e;
@@ -1220,7 +1258,7 @@ static qf_status enqueue_group(qf_plan* p, const uint8_t* bits_dev, int64_t s_be
     if (st.presplit) {
       const int64_t lda = split_ld(st.A), ldb = split_ld(st.B);
       QF_HIP(c, launch_cgemm_presplit(c->stream, M, N, K, A, B, C, Gi, shared_a ? 0 : M * lda, shared_b ? 0 : N * ldb,
-                                      M * N, rn, lda, ldb, p->precision));
+                                      (int64_t)result_elems(st), rn, lda, ldb, p->precision));
     } else {
       // folded: the group's per-chain A matrices are consecutive, so with B shared they form one
       // A of G M rows and the product's rows are the chains' results in order

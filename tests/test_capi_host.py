@@ -259,7 +259,14 @@ def test_plan_step_info_is_consistent_with_the_plan():
         fits = si.m_bits >= 8 and si.n_bits >= 7 and si.k_bits >= 4
         assert si.presplit == fits
         if si.presplit:
-            assert si.a_permuted and si.b_permuted  # the split happens in the permute
+            # the split happens in the permute, or the producing pre-split step wrote the operand
+            for node, permuted in ((si.a_node, si.a_permuted), (si.b_node, si.b_permuted)):
+                if not permuted:
+                    prod = _lib.qf_step_info()
+                    assert node >= n and lib.qf_plan_step_info(ph, node - n, C.byref(prod)) == 0
+                    assert prod.presplit and prod.out_split
+        else:
+            assert not si.out_split
         total += si.flops
     assert total == pytest.approx(inf.flops_per_slice, rel=1e-12)
     si = _lib.qf_step_info()
