@@ -285,7 +285,7 @@ qf_status qf_cgemm(qf_ctx* ctx, int precision, int64_t M, int64_t N, int64_t K, 
  * tests):
  *   0 auto, 1 tiled 128 x 64, 2 tiled 64 x 32, 3 tiled 32 x 32, 4 large 256 x 128, 5 skinny
  *   (SIMT FP32, B in LDS), 6 split-K reduction per output, 7 one thread per output, 8 tall
- *   (M large, powers of two with 8 <= N <= 64 and 16 <= K <= 64: B in LDS, A streamed).
+ *   (M large, powers of two with 8 <= N <= 64 and 8 <= K <= 64: B in LDS, A streamed).
  * QF_ERR_UNSUPPORTED if the variant does not fit the shape, QF_ERR_ARG if it is unknown. */
 qf_status qf_cgemm_variant(qf_ctx* ctx, int precision, int variant, int64_t M, int64_t N, int64_t K,
                            const void* A, const void* B, void* C, int64_t batch, int64_t sa, int64_t sb,

@@ -18,6 +18,8 @@
 //   FP32 (v_mfma_f32_16x16x4_f32, 8 MFMAs per K-step of 4 complex per lane group): the sum over
 //     k may run in any order, so MFMA t of a K-step takes, in lane group lg, the real part
 //     t % 2 of complex k = 4 lg + t / 2: each lane again reads its 32 contiguous bytes of A.
+// K = 8 (KS = 0) runs one K-step of which lane groups 2 and 3 (complex k = 8 .. 15) hold zeros in
+// both operands: half of each MFMA is wasted, which a launch bound by HBM does not notice.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <algorithm>
@@ -41,7 +43,8 @@ template <int PREC, int NT, int KS, int R>
 __global__ void __launch_bounds__(kTallThreads)
 cgemm_tall(int64_t M, const float2* __restrict__ A, const float2* __restrict__ B, float2* __restrict__ C,
            int64_t sa, int64_t sb, int64_t sc, const uint32_t* amaxA, const uint32_t* amaxB, Renorm rn) {
-  constexpr int N = 8 * NT, K = 16 * KS;
+  constexpr int N = 8 * NT, K = KS ? 16 * KS : 8, KSN = KS ? KS : 1;  // K-steps of 16 complex
+  constexpr bool HALF = KS == 0;
   // B in LDS: packed 16-bit pairs (hi plane, then lo plane for split-BF16) or FP32 complex,
   // rows padded by 16 bytes
   constexpr int LDW = (PREC == P_FP32) ? 2 * K + 4 : K + 4;  // 32-bit words per B row
@@ -81,11 +84,15 @@ cgemm_tall(int64_t M, const float2* __restrict__ A, const float2* __restrict__ B
   for (int64_t g = (int64_t)blockIdx.x * kWaves + wave; g < groups; g += (int64_t)gridDim.x * kWaves) {
     const int64_t row0 = g * 16 * R;
     // this lane's 4 complex of A per (row group, K-step)
-    f8 a[R][KS];
+    f8 a[R][KSN];
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
+      for (int s = 0; s < KSN; ++s) {
+        if (HALF && lg >= 2) {
+          a[r][s] = (f8){0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+          continue;
+        }
         const f4* p = reinterpret_cast<const f4*>(A + (row0 + 16 * r + l16) * K + 16 * s + 4 * lg);
         const f4 x0 = p[0], x1 = p[1];
         a[r][s] = (f8){x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]} * scale_a;
@@ -98,13 +105,16 @@ cgemm_tall(int64_t M, const float2* __restrict__ A, const float2* __restrict__ B
 
     if constexpr (PREC == P_FP32) {
 #pragma unroll
-      for (int s = 0; s < KS; ++s)
+      for (int s = 0; s < KSN; ++s)
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           const int n = 8 * j + (l16 >> 1);
-          const f4* bp = reinterpret_cast<const f4*>(bs + n * LDW + 2 * (16 * s + 4 * lg));
-          const f4 y0 = bp[0], y1 = bp[1];
-          const f8 b = {y0[0], y0[1], y0[2], y0[3], y1[0], y1[1], y1[2], y1[3]};
+          f8 b = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+          if (!HALF || lg < 2) {
+            const f4* bp = reinterpret_cast<const f4*>(bs + n * LDW + 2 * (16 * s + 4 * lg));
+            const f4 y0 = bp[0], y1 = bp[1];
+            b = (f8){y0[0], y0[1], y0[2], y0[3], y1[0], y1[1], y1[2], y1[3]};
+          }
 #pragma unroll
           for (int t = 0; t < 8; ++t) {
             const float bt = tall_b32(b, t, q);
@@ -115,11 +125,11 @@ cgemm_tall(int64_t M, const float2* __restrict__ A, const float2* __restrict__ B
         }
     } else {
       // operands of this lane: 4 packed pairs per (row group, K-step)
-      u4 ah[R][KS], al[R][KS];
+      u4 ah[R][KSN], al[R][KSN];
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
+        for (int s = 0; s < KSN; ++s)
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const float re = a[r][s][2 * e], im = a[r][s][2 * e + 1];
@@ -132,11 +142,12 @@ cgemm_tall(int64_t M, const float2* __restrict__ A, const float2* __restrict__ B
             }
           }
 #pragma unroll
-      for (int s = 0; s < KS; ++s)
+      for (int s = 0; s < KSN; ++s)
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           const int n = 8 * j + (l16 >> 1);
-          u4 bh = *reinterpret_cast<const u4*>(bs + n * LDW + 16 * s + 4 * lg);
+          const bool live = !HALF || lg < 2;  // K = 8: lane groups 2, 3 multiply zeros
+          u4 bh = live ? *reinterpret_cast<const u4*>(bs + n * LDW + 16 * s + 4 * lg) : (u4){0u, 0u, 0u, 0u};
 #pragma unroll
           for (int e = 0; e < 4; ++e) bh[e] = bx(bh[e]);
           if constexpr (PREC == P_FP16) {
@@ -145,7 +156,7 @@ cgemm_tall(int64_t M, const float2* __restrict__ A, const float2* __restrict__ B
               acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, ah[r][s]),
                                                                  __builtin_bit_cast(h8, bh), acc[r][j], 0, 0, 0);
           } else {
-            u4 bl = *reinterpret_cast<const u4*>(bs + N * LDW + n * LDW + 16 * s + 4 * lg);
+            u4 bl = live ? *reinterpret_cast<const u4*>(bs + N * LDW + n * LDW + 16 * s + 4 * lg) : (u4){0u, 0u, 0u, 0u};
 #pragma unroll
             for (int e = 0; e < 4; ++e) bl[e] = bx(bl[e]);
             const bf8 vbh = __builtin_bit_cast(bf8, bh), vbl = __builtin_bit_cast(bf8, bl);
@@ -187,6 +198,7 @@ cgemm_tall(int64_t M, const float2* __restrict__ A, const float2* __restrict__ B
 // Row groups per wave step: at most 4 A operand sets (K-steps x row groups) and 8 accumulator
 // tiles in registers, which leaves room for 3 or more waves per SIMD in most shapes.
 constexpr int tall_rows(int nt, int ks) {
+  ks = ks ? ks : 1;  // K = 8: one K-step
   const int r = 4 / ks < 8 / nt ? 4 / ks : 8 / nt;
   return r > 4 ? 4 : (r < 1 ? 1 : r);
 }
@@ -194,7 +206,7 @@ constexpr int tall_rows(int nt, int ks) {
 bool cgemm_tall_fits(int precision, int64_t M, int64_t N, int64_t K) {
   auto p2 = [](int64_t x) { return x > 0 && (x & (x - 1)) == 0; };
   if (precision != P_FP32 && precision != P_BF16X3 && precision != P_FP16) return false;
-  if (!p2(M) || !p2(N) || !p2(K) || N < 8 || N > 64 || K < 16 || K > 64) return false;
+  if (!p2(M) || !p2(N) || !p2(K) || N < 8 || N > 64 || K < 8 || K > 64) return false;
   return M % (16 * tall_rows((int)(N / 8), (int)(K / 16))) == 0;
 }
 
@@ -222,6 +234,7 @@ static hipError_t tall_dispatch(hipStream_t st, int64_t M, int64_t N, int64_t K,
     tall_launch<PREC, NT_, KS_>(st, M, A, B, C, batch, sa, sb, sc, amaxA, amaxB, rn);        \
     return hipGetLastError();                                                                \
   }
+  QF_TALL(1, 0) QF_TALL(2, 0) QF_TALL(4, 0) QF_TALL(8, 0)
   QF_TALL(1, 1) QF_TALL(1, 2) QF_TALL(1, 4)
   QF_TALL(2, 1) QF_TALL(2, 2) QF_TALL(2, 4)
   QF_TALL(4, 1) QF_TALL(4, 2) QF_TALL(4, 4)

@@ -212,9 +212,9 @@ def test_cgemm_variant_argument_checks_without_device():
     tall = _lib.GEMM_VARIANTS.index("tall")
     assert lib.qf_cgemm_variant(ctx, 1, 99, 4096, 32, 32, p, p, p, 1, 0, 0, 0) == _lib.QF_ERR_ARG
     assert lib.qf_cgemm_variant(ctx, 1, -1, 4096, 32, 32, p, p, p, 1, 0, 0, 0) == _lib.QF_ERR_ARG
-    # N = 4 and K = 8 are below the tall kernel's operand tiles; M = 100 is not a power of two
+    # N = 4 and K = 4 are below the tall kernel's operand tiles; M = 100 is not a power of two
     assert lib.qf_cgemm_variant(ctx, 1, tall, 4096, 4, 32, p, p, p, 1, 0, 0, 0) == _lib.QF_ERR_UNSUPPORTED
-    assert lib.qf_cgemm_variant(ctx, 1, tall, 4096, 32, 8, p, p, p, 1, 0, 0, 0) == _lib.QF_ERR_UNSUPPORTED
+    assert lib.qf_cgemm_variant(ctx, 1, tall, 4096, 32, 4, p, p, p, 1, 0, 0, 0) == _lib.QF_ERR_UNSUPPORTED
     assert lib.qf_cgemm_variant(ctx, 1, tall, 100, 32, 32, p, p, p, 1, 0, 0, 0) == _lib.QF_ERR_UNSUPPORTED
     assert lib.qf_cgemm_variant(ctx, 1, _lib.GEMM_VARIANTS.index("large"), 64, 64, 64, p, p, p, 1, 0, 0, 0) \
         == _lib.QF_ERR_UNSUPPORTED

@@ -222,7 +222,7 @@ def test_cgemm_presplit_matches_numpy(ctx, M, N, K):
 
 
 TALL_SHAPES = [(64, 8, 16), (4096, 8, 16), (65536, 32, 32), (1 << 20, 32, 32), (8192, 64, 64), (16384, 16, 64),
-               (4096, 64, 16), (2048, 8, 64), (1 << 16, 64, 32)]
+               (4096, 64, 16), (2048, 8, 64), (1 << 16, 64, 32), (4096, 64, 8), (2048, 8, 8), (1 << 16, 32, 8)]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16"])
@@ -261,10 +261,10 @@ def test_cgemm_tall_batched_and_rejects_other_shapes(ctx):
     torch.cuda.synchronize()
     bound = np.einsum("bmk,bnk->bmn", np.abs(A).astype(np.float64), np.abs(B).astype(np.float64))
     assert np.max(np.abs(dC.cpu().numpy() - ref) / bound) <= TOL["bf16x3"]
-    # K = 8 and N = 4 are below the kernel's operand tiles
+    # K = 4 and N = 4 are below the kernel's operand tiles (K = 8 runs half a K-step)
     with pytest.raises(RuntimeError):
-        cgemm(ctx, torch.zeros((4096, 8), dtype=torch.complex64, device="cuda"),
-              torch.zeros((32, 8), dtype=torch.complex64, device="cuda"), "bf16x3", variant="tall")
+        cgemm(ctx, torch.zeros((4096, 4), dtype=torch.complex64, device="cuda"),
+              torch.zeros((32, 4), dtype=torch.complex64, device="cuda"), "bf16x3", variant="tall")
     with pytest.raises(RuntimeError):
         cgemm(ctx, torch.zeros((4096, 32), dtype=torch.complex64, device="cuda"),
               torch.zeros((4, 32), dtype=torch.complex64, device="cuda"), "bf16x3", variant="tall")
