@@ -586,14 +586,8 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
   const Node& root = p->nodes.back();
   if ((int)root.labels.size() != (int)p->open.size())
     return fail(ctx, QF_ERR_PLAN, "root tensor keeps bonds: the plan does not contract the whole network");
-  for (int t = 0; t < (int)p->open.size(); ++t) {
-    const int lab = XBASE + p->open[t];
-    const int j = (int)(std::find(root.labels.begin(), root.labels.end(), lab) - root.labels.begin());
-    if (j == (int)root.labels.size()) return fail(ctx, QF_ERR_PLAN, "root misses an open output bit");
-    p->root_pos.push_back((int)root.labels.size() - 1 - j);
-  }
-  // root_pos is needed LSB-first by the accumulate kernel: bit t of j <-> open[k-1-t]
-  std::reverse(p->root_pos.begin(), p->root_pos.end());
+  for (int t = 0; t < (int)p->open.size(); ++t)
+    if (!contains(root.labels, XBASE + p->open[t])) return fail(ctx, QF_ERR_PLAN, "root misses an open output bit");
 
   // ---- persistence: a node whose dependencies are a strict subset of its consumer's is reused
   for (int i = n; i < (int)p->nodes.size() - 1; ++i) {
@@ -684,6 +678,17 @@ qf_status qf_plan_create(qf_ctx* ctx, qf_circuit* circ, const qf_plan_desc* d, q
     p->flops_per_slice += st.flops;
     if (out_node.dep_cuts == 0) p->flops_hoisted += st.flops;
     p->max_step_flops = std::max(p->max_step_flops, st.flops);
+  }
+
+  // ---- where each open output bit sits in the root, in the root's final label order (the layout
+  // pass above orders every result); needed LSB-first by the accumulate kernel: bit t of the
+  // amplitude index j <-> open[k-1-t]
+  {
+    const Node& rt = p->nodes.back();
+    for (int t = (int)p->open.size() - 1; t >= 0; --t) {
+      const int j = (int)(std::find(rt.labels.begin(), rt.labels.end(), XBASE + p->open[t]) - rt.labels.begin());
+      p->root_pos.push_back((int)rt.labels.size() - 1 - j);
+    }
   }
 
   // ---- split-K scratch: the largest need among the plan's GEMMs (forward, and the two

@@ -49,6 +49,22 @@ def test_4x4_d16_64_bitstrings_vs_state_vector(ctx, precision):
     assert rel_err(got, ref) <= BOUND[precision]
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_open_qubits_on_both_sides_with_operands_listed_small_first(ctx, precision):
+    """Every step of a row sweep written as (new cell, running tensor), so the library's roles
+    (the larger operand as A) are the reverse of the listed order, with open qubits in the first
+    and the last cell: the open output legs of both sides of the final contraction land where the
+    state vector has them."""
+    _say(f"open qubits on both sides, operands listed small first, {precision}")
+    c = generate(4, 4, 16, 3)
+    plan = sweep_plan(c, open_qubits=[0, 1, 14, 15])
+    plan = dict(plan, steps=[[b, a] for a, b in plan["steps"]])
+    bits = random_bitstrings(6, 16, 5)
+    ref = sv.open_amplitudes(c.to_text(), bits, plan["open"])
+    got = _amps(ctx, c, plan, bits, precision)
+    assert rel_err(got, ref) <= BOUND[precision]
+
+
 def test_4x4_d16_all_amplitudes_unit_norm(ctx):
     _say("4x4 d16 all 2^16 amplitudes")
     c = generate(4, 4, 16, 0)
