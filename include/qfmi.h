@@ -189,8 +189,10 @@ void qf_circuit_destroy(qf_circuit* circ);
 /* Validate a plan against a circuit and lay out its workspace (host only).  The plan is the
  * paper's contraction order (Sec. III-D), its cuts (Sec. III-A: each slice is an independent
  * network, the amplitude is the sum over slices) and its open output qubits (Sec. III-B: the root
- * keeps their output legs, 2^n_open amplitudes per pass); every step becomes a permute of each
- * operand and a complex GEMM (the transpose-GEMM-transpose scheme of Sec. III-E).  Errors:
+ * keeps their output legs, 2^n_open amplitudes per pass); every step becomes a complex GEMM with
+ * a permute of each operand that is not already in GEMM order (the transpose-GEMM-transpose scheme
+ * of Sec. III-E): results are laid out by the step that contracts their labels so that the
+ * consuming step reads most of them in place (qf_plan_step_info).  Errors:
  * QF_ERR_ARG (null arguments, unknown precision, batch not a power of two), QF_ERR_PLAN (a node used
  * twice or before it exists, a root that keeps bonds, a cut off a bond or past its bits, bad open
  * qubits), QF_ERR_UNSUPPORTED (sizes beyond the library's limits).  The message says which. */
