@@ -344,3 +344,23 @@ def test_output_order_lets_the_next_step_read_in_place():
     lib.qf_plan_destroy(ph)
     lib.qf_circuit_destroy(ch)
     lib.qf_ctx_destroy(ctx)
+
+
+def test_time_ceiling_argument_checks_without_device():
+    """qf_time_ceiling refuses unknown kinds and precisions, copy sizes that are not positive
+    multiples of 32 KiB, loops without trips, reps < 1 and null outputs before any device call
+    (the buffer pointer here is never dereferenced)."""
+    lib, ctx = _host_ctx()
+    p = C.c_void_p(256)
+    ms, work = C.c_float(), C.c_double()
+    ARG = _lib.QF_ERR_ARG
+    assert lib.qf_time_ceiling(ctx, 7, 1, p, 1 << 20, 1, C.byref(ms), C.byref(work)) == ARG  # kind
+    assert lib.qf_time_ceiling(ctx, 0, 1, p, 3 << 10, 1, C.byref(ms), C.byref(work)) == ARG  # copy size
+    assert lib.qf_time_ceiling(ctx, 0, 1, p, 0, 1, C.byref(ms), C.byref(work)) == ARG
+    assert lib.qf_time_ceiling(ctx, 1, 9, p, 100, 1, C.byref(ms), C.byref(work)) == ARG      # precision
+    assert lib.qf_time_ceiling(ctx, 1, 1, p, 0, 1, C.byref(ms), C.byref(work)) == ARG        # no trips
+    assert lib.qf_time_ceiling(ctx, 1, 1, p, 100, 0, C.byref(ms), C.byref(work)) == ARG      # reps
+    assert lib.qf_time_ceiling(ctx, 1, 1, None, 100, 1, C.byref(ms), C.byref(work)) == ARG   # buffer
+    assert lib.qf_time_ceiling(ctx, 1, 1, p, 100, 1, None, C.byref(work)) == ARG
+    assert b"qf_time_ceiling" in lib.qf_last_error(ctx)
+    lib.qf_ctx_destroy(ctx)
