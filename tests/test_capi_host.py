@@ -364,3 +364,49 @@ def test_time_ceiling_argument_checks_without_device():
     assert lib.qf_time_ceiling(ctx, 1, 1, p, 100, 1, None, C.byref(work)) == ARG
     assert b"qf_time_ceiling" in lib.qf_last_error(ctx)
     lib.qf_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("name", ["7x7-d40-bf16x3", "7x7-d40-fp32", "11x11-bf16x3"])
+def test_layout_invariants_and_permute_traffic(name):
+    """On the benchmark plans every output map stays within its step and keeps runs of at least 8
+    elements of N's low bits, every split output feeds a pre-split consumer that reads it without
+    a permute, and the permute traffic per slice stays at the level of the in-place layouts
+    (it was 487 GB for 7x7 (1+40+1) and 778 GB for 11x11 (1+24+1) with every large operand
+    permuted)."""
+    from workloads.plans import plan_11x11
+    lib, ctx = _host_ctx()
+    if name.startswith("7x7"):
+        circ = generate(7, 7, 40, 0)
+        plan, _ = plan_7x7(circ, 40)
+    else:
+        circ = generate(11, 11, 24, 0)
+        plan, _ = plan_11x11(circ)
+    precision = 0 if name.endswith("fp32") else 1
+    limit = {"7x7-d40-bf16x3": 2e11, "7x7-d40-fp32": 1.5e11, "11x11-bf16x3": 1.6e11}[name]
+    st, ch = _circuit(lib, ctx, circ)
+    assert st == 0
+    st, ph = _plan(lib, ctx, ch, plan, precision=precision)
+    assert st == 0
+    info = _lib.qf_plan_info()
+    assert lib.qf_plan_info_get(ph, C.byref(info)) == 0
+    n = info.n_qubits
+    steps = []
+    for i in range(info.n_steps):
+        si = _lib.qf_step_info()
+        assert lib.qf_plan_step_info(ph, i, C.byref(si)) == 0
+        steps.append(si)
+    consumed_split = set()
+    for si in steps:
+        if si.out_nh:
+            assert 0 < si.out_q <= si.m_bits and si.n_bits - si.out_nh >= 3
+        for node, permuted in ((si.a_node, si.a_permuted), (si.b_node, si.b_permuted)):
+            if node >= n and steps[node - n].out_split:
+                assert si.presplit and not permuted
+                consumed_split.add(node - n)
+    assert consumed_split == {i for i, si in enumerate(steps) if si.out_split}
+    if precision == 0:
+        assert not consumed_split
+    assert info.permute_bytes < limit
+    lib.qf_plan_destroy(ph)
+    lib.qf_circuit_destroy(ch)
+    lib.qf_ctx_destroy(ctx)
